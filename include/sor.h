@@ -1,0 +1,183 @@
+/*
+ * sor.h -- C ABI of libsor, a red-black successive over-relaxation (SOR)
+ * solver for AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Mittal 2014, abstract and Sec. 3.4): 2-D steady-state heat
+ * conduction -lap(u) = f on the unit square, discretised with the 5-point
+ * stencil on an n x n interior grid (mesh width h = 1/(n+1)), Dirichlet values
+ * on the four edges.  f = 0 is the paper's Laplace case.
+ *
+ * Method (Sec. 2.1 Eq. 1; Sec. 3.1 with Fig. 1-2; Algorithm 1):
+ *   every iteration updates the red cells ((i+j) even, full-array indices
+ *   with the boundary at index 0) and then the black cells, each with
+ *     s  = (N + S) + (W + E)   [+ h*h*f]
+ *     gs = 0.25 * s                       (Gauss-Seidel value)
+ *     u' = u + omega * (gs - u)           (Eq. 1 in increment form)
+ *   and the change of one iteration is max |u' - u| over all cells.  A check
+ *   runs every check_every iterations and at the last allowed iteration; the
+ *   solve stops at the first check whose change is strictly below tol.
+ *
+ * Array conventions shared by every entry point:
+ *   u         n*n interior values, row-major, u[(i-1)*n + (j-1)] = cell (i,j);
+ *             row 1 is next to the north edge.
+ *   boundary  4*n values: north edge (j = 1..n), south edge (j = 1..n),
+ *             west edge (i = 1..n), east edge (i = 1..n).  Corners are never
+ *             read by the 5-point stencil and are not part of the interface.
+ *   rhs       n*n source f of -lap(u) = f, row-major, or NULL for Laplace.
+ *   All three are DEVICE pointers on the context's GPU (e.g. the data of
+ *   torch tensors), owned by the caller, and must stay valid until the call
+ *   returns.  A host or foreign-device pointer is rejected with SOR_EINVAL.
+ *
+ * Streams: `stream` is a hipStream_t (NULL for the null stream).  All device
+ * work of a call is ordered on it; the call synchronises that stream before
+ * it returns, so results are complete on return.
+ *
+ * Errors: no exception or abort crosses this ABI.  A negative status leaves
+ * `u` unspecified; sor_last_error() describes the most recent failure of a
+ * context.  A context is not thread-safe: use one per host thread.
+ *
+ * Ownership: the library owns its padded working grids and scratch, held in
+ * the context, grown on demand and released by sor_ctx_destroy().
+ */
+#ifndef SOR_H
+#define SOR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sor_status {
+    SOR_OK = 0,              /* converged (stopping rule met) / success      */
+    SOR_NOT_CONVERGED = 1,   /* ran to the iteration limit; not an error     */
+    SOR_EINVAL = -1,         /* invalid argument                             */
+    SOR_ENOMEM = -2,         /* device or host allocation failed             */
+    SOR_EDEVICE = -3,        /* HIP runtime error                            */
+    SOR_ENONFINITE = -4,     /* a NaN or infinity appeared in the grid       */
+    SOR_EBUSY = -5,          /* resource limit (e.g. server memory budget)   */
+    SOR_ETIMEOUT = -6        /* a device-side wait exceeded its bound        */
+} sor_status;
+
+typedef struct sor_ctx sor_ctx;
+
+/* Outcome of a solve. */
+typedef struct sor_result {
+    int64_t iterations;       /* plain solves: the 1-based iteration whose check
+                                 passed, else max_iters.  Mixed: total inner
+                                 iterations run.                              */
+    double final_max_delta;   /* plain: max |u' - u| of the last checked
+                                 iteration.  Mixed: max |correction| of the
+                                 last correction (FP64).                      */
+    int32_t converged;        /* 1 when the stopping rule was met            */
+    int32_t outer_steps;      /* mixed: corrections applied; plain: 0        */
+    double rel_residual;      /* mixed: final ||r||_2 / ||b||_2; plain: NaN  */
+    int64_t passes;           /* sweep kernel passes that did work           */
+} sor_result;
+
+/* Library version string, e.g. "sor 0.1.0 gfx950". */
+const char *sor_version(void);
+
+/* Create a context bound to HIP device `device`.  Returns SOR_OK and *out, or
+ * SOR_EINVAL (bad device / NULL out) or SOR_EDEVICE. */
+sor_status sor_ctx_create(int device, sor_ctx **out);
+
+/* Release the context and every device buffer it owns.  NULL is a no-op. */
+void sor_ctx_destroy(sor_ctx *ctx);
+
+/* Message of the context's most recent failure ("" if none).  The string is
+ * owned by the context and valid until its next call. */
+const char *sor_last_error(const sor_ctx *ctx);
+
+/* Sweep kernel family used by the plain solves:
+ *   SOR_KERNEL_BLOCKED  (default) one pass per `iters_per_pass` iterations:
+ *                       each wavefront streams a column strip of a row segment
+ *                       through registers and applies both colours of several
+ *                       iterations before writing back (temporal blocking).
+ *   SOR_KERNEL_SIMPLE   one launch per colour per iteration, one thread per
+ *                       cell of that colour (the paper's red phase, barrier,
+ *                       black phase, barrier, as separate launches).        */
+enum { SOR_KERNEL_BLOCKED = 0, SOR_KERNEL_SIMPLE = 1 };
+sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
+
+/* Tiling of the blocked kernel for one storage precision (64, 32 or 16 bits):
+ * iters_per_pass in 1..8 (iterations applied per HBM pass) and seg_rows, the
+ * rows of output per wavefront (even, 8..1024).  0 in a field means "keep". */
+typedef struct sor_tiling {
+    int32_t iters_per_pass;
+    int32_t seg_rows;
+} sor_tiling;
+sor_status sor_ctx_set_tiling(sor_ctx *ctx, int32_t bits, const sor_tiling *t);
+sor_status sor_ctx_get_tiling(const sor_ctx *ctx, int32_t bits, sor_tiling *t);
+
+/*
+ * Plain FP64 red-black SOR (Sec. 2.1 Eq. 1, Sec. 3.1, Algorithm 1).
+ *   u           in: initial guess; out: final iterate (device, n*n)
+ *   boundary    device, 4*n;  rhs: device n*n or NULL
+ *   n           >= 1;  omega in (0, 2) (Sec. 2.1);  tol >= 0
+ *   max_iters   >= 1;  check_every >= 1 (Algorithm 1's K)
+ *   out         receives the outcome (required)
+ *   max_hist    optional HOST array of max_iters doubles: entry k-1 receives
+ *               the change of iteration k for k = 1..out->iterations.
+ * Returns SOR_OK (converged), SOR_NOT_CONVERGED, SOR_ENONFINITE (u holds the
+ * non-finite iterate), SOR_EINVAL, SOR_ENOMEM or SOR_EDEVICE.
+ */
+sor_status sor_solve_f64(sor_ctx *ctx, double *u, const double *boundary,
+                         const double *rhs, int32_t n, double omega, double tol,
+                         int64_t max_iters, int64_t check_every, void *stream,
+                         sor_result *out, double *max_hist);
+
+/*
+ * The same method with float storage and float arithmetic: omega is rounded
+ * once to float, the source enters as fl32(h*h*f) with the product formed in
+ * double, and changes are compared with tol in double.  Arguments as for
+ * sor_solve_f64 with float arrays.
+ */
+sor_status sor_solve_f32(sor_ctx *ctx, float *u, const float *boundary,
+                         const float *rhs, int32_t n, double omega, double tol,
+                         int64_t max_iters, int64_t check_every, void *stream,
+                         sor_result *out, double *max_hist);
+
+/*
+ * FP64 residual of the h*h-scaled system 4u - (interior neighbours) = b,
+ * b = h*h*f + (boundary neighbours):
+ *   r = (h*h*f + ((N + S) + (W + E))) - 4u   at every interior cell.
+ *   r      optional DEVICE array of n*n doubles receiving r (NULL: not stored)
+ *   stats  HOST array of 3 doubles: { sum r^2, sum b^2, max |r| }; the sums
+ *          use a fixed, launch-independent order (deterministic).
+ */
+sor_status sor_residual_f64(sor_ctx *ctx, const double *u,
+                            const double *boundary, const double *rhs,
+                            int32_t n, double *r, double *stats, void *stream);
+
+/*
+ * Mixed precision: FP64 defect correction around reduced-precision SOR.
+ *   repeat: r = b - A u in FP64 (sor_residual_f64's expression);
+ *           rel = ||r||_2 / ||b||_2; stop when rel <= rel_tol or after
+ *           max_outer corrections;
+ *           solve A e = r approximately with inner_iters red-black SOR
+ *           iterations from e = 0 under a zero boundary, with e and the
+ *           right-hand side stored in `inner_bits` (32: float; 16: IEEE
+ *           binary16) and float arithmetic;  u = u + e in FP64.
+ *   The inner right-hand side is fl(r * 2^p), p = floor(log2(target/max|r|)),
+ *   target = 1 for 32-bit and 2^14*h*h/0.0737 for 16-bit storage (0.0737
+ *   bounds the infinity norm of the inverse of the unscaled 5-point operator
+ *   on the unit square, keeping the scaled correction below about 2^14);
+ *   the correction is added as u + (double)e * 2^-p.
+ *   inner_iters <= 0 selects 2*n.  rel_hist: optional HOST array of
+ *   max_outer + 1 doubles receiving rel before each correction and at exit.
+ * Returns SOR_OK when rel <= rel_tol was reached, else SOR_NOT_CONVERGED, or
+ * an error status.
+ */
+sor_status sor_solve_mixed(sor_ctx *ctx, double *u, const double *boundary,
+                           const double *rhs, int32_t n, double omega,
+                           double rel_tol, int64_t max_outer, int32_t inner_bits,
+                           int64_t inner_iters, void *stream, sor_result *out,
+                           double *rel_hist);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOR_H */

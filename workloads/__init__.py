@@ -1,0 +1,128 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the bench.
+
+This module only draws numbers and fixes problem parameters; it contains none
+of the solver's arithmetic.  Both the CPU oracle and the GPU library receive
+exactly these arrays.
+
+Random streams: ``numpy.random.default_rng(seed)`` (PCG64).  Draw order for a
+grid: boundary edges north, south, west, east (one draw of 4n values), then
+the source f row-major.  For batches and request streams the per-item draws are
+taken in item order: side length, then boundary, then f.
+
+Workloads (sizes are interior nodes per side; h = 1/(n+1)):
+  * ``laplace_top_edge`` -- Laplace, north edge = value, other edges 0,
+    interior 0 (the paper's heat-conduction set-up, Sec. 3.4).
+  * ``laplace_random_boundary`` -- Laplace, each boundary node U[0, 100].
+  * ``poisson_manufactured`` -- -lap u = f with f i.i.d. N(0,1) plus the
+    manufactured term 2 pi^2 sin(pi x) sin(pi y), zero boundary.
+  * ``batch_grids`` -- many grids with log-uniform side lengths.
+  * ``request_stream`` -- seeded Poisson arrivals of solve requests.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def omega_opt(n: int) -> float:
+    """Young's optimal relaxation factor 2 / (1 + sin(pi h)), h = 1/(n+1)."""
+    return 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+
+
+@dataclass
+class Grid:
+    n: int
+    u0: np.ndarray              # n x n initial interior (float64)
+    bdy: np.ndarray             # 4n boundary values: N, S, W, E (float64)
+    f: np.ndarray | None        # n x n source, or None for Laplace
+    omega: float
+    tol: float = 1e-8
+    max_iters: int = 100000
+    check_every: int = 1
+    meta: dict = field(default_factory=dict)
+
+
+def laplace_top_edge(n: int = 256, top: float = 100.0, tol: float = 1e-6,
+                     max_iters: int = 5000, check_every: int = 1) -> Grid:
+    bdy = np.zeros(4 * n, dtype=np.float64)
+    bdy[:n] = top
+    return Grid(n, np.zeros((n, n)), bdy, None, omega_opt(n), tol, max_iters,
+                check_every, {"name": f"laplace_top_edge_{n}"})
+
+
+def laplace_random_boundary(n: int = 4096, seed: int = 2, tol: float = 1e-8,
+                            max_iters: int = 1000, check_every: int = 10) -> Grid:
+    rng = np.random.default_rng(seed)
+    bdy = rng.uniform(0.0, 100.0, size=4 * n)
+    return Grid(n, np.zeros((n, n)), bdy, None, omega_opt(n), tol, max_iters,
+                check_every, {"name": f"laplace_random_boundary_{n}", "seed": seed})
+
+
+def manufactured_term(n: int) -> np.ndarray:
+    """2 pi^2 sin(pi x_j) sin(pi y_i) on the interior nodes x_j = j h, y_i = i h."""
+    h = 1.0 / (n + 1)
+    s = np.sin(np.pi * h * np.arange(1, n + 1))
+    return 2.0 * np.pi ** 2 * np.outer(s, s)
+
+
+def poisson_manufactured(n: int = 4096, seed: int = 3, noise: bool = True) -> Grid:
+    rng = np.random.default_rng(seed)
+    bdy = np.zeros(4 * n, dtype=np.float64)
+    f = manufactured_term(n)
+    if noise:
+        f = f + rng.standard_normal((n, n))
+    return Grid(n, np.zeros((n, n)), bdy, f, omega_opt(n), 1e-10, 100000, 1,
+                {"name": f"poisson_manufactured_{n}", "seed": seed})
+
+
+def random_grid(rng: np.random.Generator, n: int, with_f: bool,
+                tol: float = 1e-8) -> Grid:
+    bdy = rng.uniform(0.0, 100.0, size=4 * n)
+    f = rng.standard_normal((n, n)) if with_f else None
+    return Grid(n, np.zeros((n, n)), bdy, f, omega_opt(n), tol, 1000000, 1)
+
+
+def batch_grids(count: int = 512, lo: int = 64, hi: int = 1024, seed: int = 4,
+                tol: float = 1e-8) -> list[Grid]:
+    """count grids, side n = round(exp(U(ln lo, ln hi))), f on odd indices."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g in range(count):
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        grid = random_grid(rng, n, with_f=(g % 2 == 1), tol=tol)
+        grid.meta = {"index": g}
+        out.append(grid)
+    return out
+
+
+@dataclass
+class Request:
+    arrival_s: float
+    grid: Grid
+
+
+def request_stream(count: int = 2000, rate_per_s: float = 100.0, lo: int = 128,
+                   hi: int = 2048, seed: int = 5, rel_tol: float = 1e-8) -> list[Request]:
+    """Poisson arrivals (exponential gaps at rate_per_s) of solve requests."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        grid = random_grid(rng, n, with_f=True, tol=rel_tol)
+        grid.meta = {"index": k}
+        out.append(Request(t, grid))
+    return out
+
+
+def random_small(seed: int, n: int, with_f: bool = True, omega: float | None = None,
+                 nonzero_u0: bool = False) -> Grid:
+    """Small seeded grid for parity tests (random boundary, f, optional u0)."""
+    rng = np.random.default_rng(seed)
+    bdy = rng.uniform(0.0, 100.0, size=4 * n)
+    f = rng.standard_normal((n, n)) * 1000.0 if with_f else None
+    u0 = rng.uniform(0.0, 100.0, size=(n, n)) if nonzero_u0 else np.zeros((n, n))
+    return Grid(n, u0, bdy, f, omega_opt(n) if omega is None else omega)
