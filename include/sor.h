@@ -102,7 +102,7 @@ enum { SOR_KERNEL_BLOCKED = 0, SOR_KERNEL_SIMPLE = 1 };
 sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
 
 /* Tiling of the blocked kernel for one storage precision (64, 32 or 16 bits):
- * iters_per_pass in 1..8 (iterations applied per HBM pass) and seg_rows, the
+ * iters_per_pass in {1, 2, 3, 4, 6, 8} (iterations applied per HBM pass) and seg_rows, the
  * rows of output per wavefront (even, 8..1024).  0 in a field means "keep". */
 typedef struct sor_tiling {
     int32_t iters_per_pass;
@@ -110,6 +110,15 @@ typedef struct sor_tiling {
 } sor_tiling;
 sor_status sor_ctx_set_tiling(sor_ctx *ctx, int32_t bits, const sor_tiling *t);
 sor_status sor_ctx_get_tiling(const sor_ctx *ctx, int32_t bits, sor_tiling *t);
+
+/* Kernel timing for measurement.  While profiling is on, every sweep-kernel
+ * launch of the plain and mixed solves is bracketed by HIP events on the
+ * caller's stream; passes that did work add their duration to a running
+ * total.  sor_ctx_get_profile returns the total milliseconds and the number of
+ * timed launches since profiling was last switched on. */
+sor_status sor_ctx_set_profiling(sor_ctx *ctx, int32_t on);
+sor_status sor_ctx_get_profile(const sor_ctx *ctx, double *kernel_ms,
+                               int64_t *launches);
 
 /*
  * Plain FP64 red-black SOR (Sec. 2.1 Eq. 1, Sec. 3.1, Algorithm 1).

@@ -1,0 +1,292 @@
+"""Red-black SOR for AMD MI355X (gfx950): Python binding of libsor.
+
+Thin ctypes marshalling over the C ABI in ``include/sor.h``; every step of a
+solve runs in the library's HIP kernels.  PyTorch supplies device memory and
+streams only: arrays are torch tensors on a ROCm device, passed by data
+pointer, and work is ordered on ``torch.cuda.current_stream()``.
+
+The library must have been built (``python -m paper_1401_0763_amd.build`` or
+``__graft_entry__.build()``); importing the solver functions without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import threading
+from dataclasses import dataclass
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsor.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY, ETIMEOUT = (
+    0, 1, -1, -2, -3, -4, -5, -6)
+KERNEL_BLOCKED, KERNEL_SIMPLE = 0, 1
+
+_STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", EINVAL: "EINVAL",
+                 ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
+                 EBUSY: "EBUSY", ETIMEOUT: "ETIMEOUT"}
+
+
+class SorError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64),
+                ("final_max_delta", ctypes.c_double),
+                ("converged", ctypes.c_int32),
+                ("outer_steps", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double),
+                ("passes", ctypes.c_int64)]
+
+
+class _Tiling(ctypes.Structure):
+    _fields_ = [("iters_per_pass", ctypes.c_int32), ("seg_rows", ctypes.c_int32)]
+
+
+@dataclass
+class Result:
+    status: int
+    iterations: int
+    final_max_delta: float
+    converged: bool
+    outer_steps: int
+    rel_residual: float
+    passes: int
+    hist: list | None = None
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def _declare(lib):
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.sor_version.restype = ctypes.c_char_p
+    lib.sor_version.argtypes = []
+    lib.sor_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.sor_ctx_create.restype = ctypes.c_int
+    lib.sor_ctx_destroy.argtypes = [P]
+    lib.sor_ctx_destroy.restype = None
+    lib.sor_last_error.argtypes = [P]
+    lib.sor_last_error.restype = ctypes.c_char_p
+    lib.sor_ctx_set_profiling.argtypes = [P, i32]
+    lib.sor_ctx_set_profiling.restype = ctypes.c_int
+    lib.sor_ctx_get_profile.argtypes = [P, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.sor_ctx_get_profile.restype = ctypes.c_int
+    lib.sor_ctx_set_kernel.argtypes = [P, i32]
+    lib.sor_ctx_set_kernel.restype = ctypes.c_int
+    lib.sor_ctx_set_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_ctx_set_tiling.restype = ctypes.c_int
+    lib.sor_ctx_get_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_ctx_get_tiling.restype = ctypes.c_int
+    solve_args = [P, P, P, P, i32, dbl, dbl, i64, i64, P,
+                  ctypes.POINTER(_Result), P]
+    for name in ("sor_solve_f64", "sor_solve_f32"):
+        getattr(lib, name).argtypes = solve_args
+        getattr(lib, name).restype = ctypes.c_int
+    lib.sor_residual_f64.argtypes = [P, P, P, P, i32, P, P, P]
+    lib.sor_residual_f64.restype = ctypes.c_int
+    lib.sor_solve_mixed.argtypes = [P, P, P, P, i32, dbl, dbl, i64, i32, i64, P,
+                                    ctypes.POINTER(_Result), P]
+    lib.sor_solve_mixed.restype = ctypes.c_int
+
+
+def load_library():
+    """Load libsor.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(
+                    f"{LIB_PATH} is missing: build it with "
+                    "`python -m paper_1401_0763_amd.build`")
+            lib = ctypes.CDLL(LIB_PATH)
+            _declare(lib)
+            _lib = lib
+    return _lib
+
+
+def version() -> str:
+    return load_library().sor_version().decode()
+
+
+class Context:
+    """A libsor context bound to one device (owns the working grids)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.sor_ctx_create(int(device), ctypes.byref(h))
+        if st != OK:
+            raise SorError(st, f"sor_ctx_create(device={device}) failed")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sor_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return self.lib.sor_last_error(self.handle).decode()
+
+    def _check(self, st, allow=(OK, NOT_CONVERGED)):
+        if st not in allow:
+            raise SorError(st, self.error())
+        return st
+
+    def set_kernel(self, kernel: int):
+        self._check(self.lib.sor_ctx_set_kernel(self.handle, int(kernel)))
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.sor_ctx_set_profiling(self.handle, int(bool(on))))
+
+    def profile(self) -> tuple[float, int]:
+        """(total sweep-kernel milliseconds, timed launches) since profiling on."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        self._check(self.lib.sor_ctx_get_profile(self.handle, ctypes.byref(ms),
+                                                 ctypes.byref(k)))
+        return ms.value, k.value
+
+    def set_tiling(self, bits: int, iters_per_pass: int = 0, seg_rows: int = 0):
+        t = _Tiling(int(iters_per_pass), int(seg_rows))
+        self._check(self.lib.sor_ctx_set_tiling(self.handle, int(bits), ctypes.byref(t)))
+
+    def get_tiling(self, bits: int) -> tuple[int, int]:
+        t = _Tiling()
+        self._check(self.lib.sor_ctx_get_tiling(self.handle, int(bits), ctypes.byref(t)))
+        return t.iters_per_pass, t.seg_rows
+
+
+_contexts: dict[int, Context] = {}
+
+
+def context(device: int | None = None) -> Context:
+    """Per-device default context (created on first use)."""
+    import torch
+    if device is None:
+        device = torch.cuda.current_device()
+    with _lock:
+        ctx = _contexts.get(device)
+    if ctx is None:
+        ctx = Context(device)
+        with _lock:
+            _contexts[device] = ctx
+    return ctx
+
+
+def _stream_handle(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _check_tensor(name, t, dtype, shape):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _result(st, r: _Result, hist=None) -> Result:
+    return Result(st, r.iterations, r.final_max_delta, bool(r.converged),
+                  r.outer_steps, r.rel_residual, r.passes, hist)
+
+
+def _solve_plain(fn, dtype, u, boundary, rhs, omega, tol, max_iters,
+                 check_every, hist, ctx):
+    n = u.shape[0]
+    pu = _check_tensor("u", u, dtype, (n, n))
+    pb = _check_tensor("boundary", boundary, dtype, (4 * n,))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, dtype, (n, n))
+    ctx = ctx or context(u.device.index)
+    res = _Result()
+    hbuf = (ctypes.c_double * int(max_iters))() if hist else None
+    st = fn(ctx.handle, pu, pb, pf, int(n), float(omega), float(tol),
+            int(max_iters), int(check_every), _stream_handle(u),
+            ctypes.byref(res), hbuf)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    h = list(hbuf[: res.iterations]) if hist else None
+    return _result(st, res, h)
+
+
+def solve_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
+              check_every=1, hist=False, ctx: Context | None = None) -> Result:
+    """FP64 red-black SOR in place on u (n x n float64 CUDA tensor)."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    ctx = ctx or context(u.device.index)
+    return _solve_plain(ctx.lib.sor_solve_f64, torch.float64, u, boundary, rhs,
+                        omega, tol, max_iters, check_every, hist, ctx)
+
+
+def solve_f32(u, boundary, rhs=None, omega=None, tol=1e-5, max_iters=100000,
+              check_every=1, hist=False, ctx: Context | None = None) -> Result:
+    """Float-storage red-black SOR in place on u (n x n float32 CUDA tensor)."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    ctx = ctx or context(u.device.index)
+    return _solve_plain(ctx.lib.sor_solve_f32, torch.float32, u, boundary, rhs,
+                        omega, tol, max_iters, check_every, hist, ctx)
+
+
+def residual_f64(u, boundary, rhs=None, r=None, ctx: Context | None = None):
+    """Return (sum r^2, sum b^2, max|r|); fills r (n x n float64) if given."""
+    import torch
+    n = u.shape[0]
+    pu = _check_tensor("u", u, torch.float64, (n, n))
+    pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
+    pr = None if r is None else _check_tensor("r", r, torch.float64, (n, n))
+    ctx = ctx or context(u.device.index)
+    stats = (ctypes.c_double * 3)()
+    st = ctx.lib.sor_residual_f64(ctx.handle, pu, pb, pf, int(n), pr, stats,
+                                  _stream_handle(u))
+    ctx._check(st, (OK,))
+    return float(stats[0]), float(stats[1]), float(stats[2])
+
+
+def solve_mixed(u, boundary, rhs=None, omega=None, rel_tol=1e-10, max_outer=50,
+                inner_bits=32, inner_iters=0, hist=False,
+                ctx: Context | None = None) -> Result:
+    """FP64 defect correction around FP32 or binary16-storage SOR, in place on u."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    pu = _check_tensor("u", u, torch.float64, (n, n))
+    pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
+    ctx = ctx or context(u.device.index)
+    res = _Result()
+    hbuf = (ctypes.c_double * (int(max_outer) + 1))() if hist else None
+    st = ctx.lib.sor_solve_mixed(ctx.handle, pu, pb, pf, int(n), float(omega),
+                                 float(rel_tol), int(max_outer), int(inner_bits),
+                                 int(inner_iters), _stream_handle(u),
+                                 ctypes.byref(res), hbuf)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    h = list(hbuf[: res.outer_steps + 1]) if hist else None
+    return _result(st, res, h)

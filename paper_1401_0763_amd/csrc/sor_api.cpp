@@ -1,0 +1,543 @@
+// Host runtime of libsor: the C ABI declared in include/sor.h.
+//
+// Control flow of a plain solve (Algorithm 1 of Mittal 2014, restated):
+//   for iter = 1..max_iters: red phase, black phase; on a check iteration
+//   (iter % K == 0 or iter == max_iters) stop when the iteration's largest
+//   change is strictly below tol.
+// On the GPU each "pass" applies T iterations; the last wavefront of a pass
+// evaluates the stopping rule for those T iterations on the device and sets a
+// stop flag that makes every later pass exit at once.  The host therefore
+// enqueues passes in chunks without waiting, and synchronises once per chunk.
+// When the rule is met at an iteration inside a pass, that pass's output has
+// gone too far: its input grid is still intact (ping-pong, and every later
+// pass exited early), so the pass is re-run from its input with exactly the
+// iterations needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sor.h"
+#include "sor_internal.h"
+
+using namespace sor;
+
+namespace {
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+enum BufRole {
+  kGridA64, kGridB64, kF64Buf,     // plain FP64 solve; U64 of the mixed solve
+  kGridA32, kGridB32, kF32Buf,     // plain FP32 solve; inner grids of mixed
+  kLoRhs,                          // inner right-hand side of the mixed solve
+  kPartials, kStats, kCtlBuf,
+  kNumRoles
+};
+
+}  // namespace
+
+struct sor_ctx {
+  int device = 0;
+  std::string err;
+  int kernel = SOR_KERNEL_BLOCKED;
+  sor_tiling tiling[3] = {{4, 64}, {4, 64}, {4, 64}};   // by Prec
+  DevBuf bufs[kNumRoles];
+  Ctl *host_ctl = nullptr;                             // pinned mirror
+  double *host_stats = nullptr;                        // pinned [4]
+  bool prof = false;                                   // time sweep launches
+  std::vector<hipEvent_t> events;                      // start/stop pairs
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+sor_status fail(sor_ctx *c, sor_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                   \
+  do {                                                                       \
+    hipError_t e_ = (expr);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return fail((ctx), SOR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+sor_status ensure(sor_ctx *c, BufRole role, size_t bytes) {
+  DevBuf &b = c->bufs[role];
+  if (b.bytes >= bytes) return SOR_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(c, SOR_ENOMEM, "cannot allocate %zu bytes of device memory", bytes);
+  }
+  // Zero once so margins never hold stale bit patterns.
+  e = hipMemset(b.p, 0, bytes);
+  if (e != hipSuccess) return fail(c, SOR_EDEVICE, "hipMemset: %s", hipGetErrorString(e));
+  b.bytes = bytes;
+  return SOR_OK;
+}
+
+template <typename T>
+T *origin(sor_ctx *c, BufRole role, const Layout &L) {
+  return (T *)c->bufs[role].p + L.origin_off();
+}
+
+bool is_device_ptr(sor_ctx *c, const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) &&
+         a.device == c->device;
+}
+
+sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
+                        const void *rhs, int32_t n, double omega) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (n < 1 || n > (1 << 20)) return fail(c, SOR_EINVAL, "n = %d out of range", n);
+  if (!(omega > 0.0 && omega < 2.0))
+    return fail(c, SOR_EINVAL, "omega = %g outside (0, 2)", omega);
+  if (!is_device_ptr(c, u)) return fail(c, SOR_EINVAL, "u is not a device pointer on device %d", c->device);
+  if (!is_device_ptr(c, bdy)) return fail(c, SOR_EINVAL, "boundary is not a device pointer on device %d", c->device);
+  if (rhs && !is_device_ptr(c, rhs)) return fail(c, SOR_EINVAL, "rhs is not a device pointer on device %d", c->device);
+  HIP_TRY(c, hipSetDevice(c->device));
+  return SOR_OK;
+}
+
+int prec_index(int bits) { return bits == 64 ? kF64 : bits == 32 ? kF32 : bits == 16 ? kF16 : -1; }
+
+GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *in,
+                   void *out, const void *F, double omega) {
+  GridView v;
+  v.in = in;
+  v.out = out;
+  v.F = F;
+  v.pitch = L.pitch;
+  v.n = L.n;
+  const BlockGeom g = block_geom(prec, t.iters_per_pass);
+  v.nstrips = (L.n + 1 + g.CW - 1) / g.CW;
+  v.seg_rows = t.seg_rows;
+  v.nseg = (L.n + 1 + t.seg_rows - 1) / t.seg_rows;
+  v.omega = omega;
+  return v;
+}
+
+struct PassRec {
+  const void *in;
+  void *out;
+  long long it0;
+  int T;
+};
+
+// Event pair k of the context's pool (grown on demand).
+sor_status prof_events(sor_ctx *c, size_t k, hipEvent_t *a, hipEvent_t *b) {
+  while (c->events.size() < 2 * (k + 1)) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  *a = c->events[2 * k];
+  *b = c->events[2 * k + 1];
+  return SOR_OK;
+}
+
+// Run red-black SOR sweeps on the packed grids A/B (same layout L) until the
+// stopping rule or max_iters.  On return *result_grid is the grid holding the
+// final iterate.  hist (host, may be null) receives per-iteration changes.
+sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
+                      const void *F, double omega, const Sched &sc,
+                      hipStream_t s, sor_result *res, double *hist,
+                      void **result_grid) {
+  Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
+  HIP_TRY(c, launch_ctl_reset(ctl, s));
+  const sor_tiling tl = c->tiling[prec];
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
+  const int T = simple ? 1 : tl.iters_per_pass;
+  GridView base = make_view(L, prec, tl, A, B, F, omega);
+
+  std::vector<PassRec> recs;
+  long long done = 0;               // iterations enqueued
+  long long chunk = 1;              // passes per chunk
+  void *cur = A, *oth = B;
+  long long reruns = 0;
+  *result_grid = A;
+  res->converged = 0;
+  res->iterations = sc.max_iters;
+  res->final_max_delta = NAN;
+  for (;;) {
+    const long long chunk_it0 = done;
+    recs.clear();
+    // Enqueue up to `chunk` passes (a truncated pass when < T iterations remain).
+    for (long long k = 0; k < chunk && done < sc.max_iters; ++k) {
+      const int Tp = (int)std::min<long long>(T, sc.max_iters - done);
+      GridView v = base;
+      v.in = cur;
+      v.out = simple ? cur : oth;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c->prof) {
+        sor_status pst = prof_events(c, (size_t)k, &e0, &e1);
+        if (pst != SOR_OK) return pst;
+        HIP_TRY(c, hipEventRecord(e0, s));
+      }
+      if (simple) {
+        HIP_TRY(c, launch_simple_iteration(prec, v, ctl, sc, s));
+      } else {
+        HIP_TRY(c, launch_blocked_pass(prec, T, v, ctl, sc, Tp, s));
+        std::swap(cur, oth);
+      }
+      if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
+      recs.push_back({v.in, v.out, done, Tp});
+      done += Tp;
+      if (done - chunk_it0 >= kHistCap - kTMax) break;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const Ctl &h = *c->host_ctl;
+    const long long hist_end = h.stop ? h.stop_iter : done;
+    if (c->prof) {
+      for (size_t k = 0; k < recs.size(); ++k) {
+        if (h.stop && recs[k].it0 >= h.stop_iter) break;   // exited early
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+    if (hist) {
+      for (long long it = chunk_it0 + 1; it <= std::min(hist_end, sc.max_iters); ++it)
+        hist[it - 1] = h.hist[(it - 1) % kHistCap];
+    }
+    if (h.stop) {
+      res->iterations = h.stop_iter;
+      res->final_max_delta = h.stop_max;
+      res->passes = h.passes_done + reruns;
+      // Locate the pass in which the rule was met.
+      const PassRec *pr = nullptr;
+      for (const PassRec &r : recs)
+        if (h.stop_iter > r.it0 && h.stop_iter <= r.it0 + r.T) { pr = &r; break; }
+      if (!pr) return fail(c, SOR_EDEVICE, "stop iteration %lld outside the chunk", h.stop_iter);
+      if (h.stop == 2) {
+        *result_grid = pr->out;
+        return fail(c, SOR_ENONFINITE, "non-finite value in the grid by iteration %lld", h.stop_iter);
+      }
+      res->converged = 1;
+      if (h.stop_iter == pr->it0 + pr->T || simple) {
+        *result_grid = pr->out;
+      } else {
+        // Rule met inside the pass: redo it from its intact input.
+        GridView v = base;
+        v.in = pr->in;
+        v.out = pr->out;
+        const int Tr = (int)(h.stop_iter - pr->it0);
+        HIP_TRY(c, launch_blocked_pass(prec, T, v, nullptr, sc, Tr, s));
+        ++reruns;
+        res->passes = h.passes_done + reruns;
+        *result_grid = pr->out;
+      }
+      return SOR_OK;
+    }
+    if (done >= sc.max_iters) {
+      res->iterations = sc.max_iters;
+      res->final_max_delta = h.last_max;
+      res->passes = h.passes_done;
+      *result_grid = cur;
+      return SOR_NOT_CONVERGED;
+    }
+    chunk = std::min<long long>(chunk * 2, 64);
+  }
+}
+
+sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K) {
+  if (!(tol >= 0.0)) return fail(c, SOR_EINVAL, "tol = %g must be >= 0", tol);
+  if (max_iters < 1) return fail(c, SOR_EINVAL, "max_iters must be >= 1");
+  if (K < 1) return fail(c, SOR_EINVAL, "check_every must be >= 1");
+  return SOR_OK;
+}
+
+template <typename T>
+sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
+                       int32_t n, double omega, double tol, int64_t max_iters,
+                       int64_t K, void *stream, sor_result *out, double *hist) {
+  sor_status st = check_common(c, u, bdy, rhs, n, omega);
+  if (st != SOR_OK) return st;
+  if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
+  if ((st = check_sched(c, tol, max_iters, K)) != SOR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout L = make_layout(n, prec);
+  const size_t bytes = (size_t)L.elems() * sizeof(T);
+  const BufRole ra = prec == kF64 ? kGridA64 : kGridA32;
+  const BufRole rb = prec == kF64 ? kGridB64 : kGridB32;
+  const BufRole rf = prec == kF64 ? kF64Buf : kF32Buf;
+  if ((st = ensure(c, ra, bytes)) || (st = ensure(c, rb, bytes))) return st;
+  if (rhs && (st = ensure(c, rf, bytes))) return st;
+  T *A = origin<T>(c, ra, L), *B = origin<T>(c, rb, L);
+  T *F = rhs ? origin<T>(c, rf, L) : nullptr;
+  HIP_TRY(c, launch_pack(prec, u, bdy, A, B, L.pitch, n, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(prec, rhs, F, L.pitch, n, s));
+  *out = sor_result{};
+  out->rel_residual = NAN;
+  const Sched sc{max_iters, K, tol};
+  void *res_grid = A;
+  st = run_sweeps(c, prec, L, A, B, F, omega, sc, s, out, hist, &res_grid);
+  if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
+    HIP_TRY(c, launch_unpack(prec, res_grid, u, L.pitch, n, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sor_version(void) { return "sor 0.1.0 gfx950"; }
+
+sor_status sor_ctx_create(int device, sor_ctx **out) {
+  if (!out) return SOR_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return SOR_EDEVICE;
+  }
+  if (device < 0 || device >= count) return SOR_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return SOR_EDEVICE;
+  sor_ctx *c = new (std::nothrow) sor_ctx;
+  if (!c) return SOR_ENOMEM;
+  c->device = device;
+  if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void **)&c->host_stats, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    sor_ctx_destroy(c);
+    return SOR_ENOMEM;
+  }
+  if (ensure(c, kCtlBuf, sizeof(Ctl)) != SOR_OK) {
+    sor_ctx_destroy(c);
+    return SOR_ENOMEM;
+  }
+  *out = c;
+  return SOR_OK;
+}
+
+void sor_ctx_destroy(sor_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (DevBuf &b : c->bufs)
+    if (b.p) (void)hipFree(b.p);
+  if (c->host_ctl) (void)hipHostFree(c->host_ctl);
+  if (c->host_stats) (void)hipHostFree(c->host_stats);
+  delete c;
+}
+
+const char *sor_last_error(const sor_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+sor_status sor_ctx_set_profiling(sor_ctx *c, int32_t on) {
+  if (!c) return SOR_EINVAL;
+  c->prof = on != 0;
+  c->prof_ms = 0.0;
+  c->prof_launches = 0;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_get_profile(const sor_ctx *c, double *kernel_ms, int64_t *launches) {
+  if (!c || !kernel_ms || !launches) return SOR_EINVAL;
+  *kernel_ms = c->prof_ms;
+  *launches = c->prof_launches;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_set_kernel(sor_ctx *c, int32_t kernel) {
+  if (!c) return SOR_EINVAL;
+  if (kernel != SOR_KERNEL_BLOCKED && kernel != SOR_KERNEL_SIMPLE)
+    return fail(c, SOR_EINVAL, "unknown kernel %d", kernel);
+  c->kernel = kernel;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_set_tiling(sor_ctx *c, int32_t bits, const sor_tiling *t) {
+  if (!c || !t) return SOR_EINVAL;
+  const int p = prec_index(bits);
+  if (p < 0) return fail(c, SOR_EINVAL, "bits must be 64, 32 or 16");
+  sor_tiling nt = c->tiling[p];
+  if (t->iters_per_pass) {
+    if (!blocked_T_supported(t->iters_per_pass))
+      return fail(c, SOR_EINVAL, "iters_per_pass must be 1, 2, 3, 4, 6 or 8");
+    nt.iters_per_pass = t->iters_per_pass;
+  }
+  if (t->seg_rows) {
+    if (t->seg_rows < 8 || t->seg_rows > 1024 || (t->seg_rows & 1))
+      return fail(c, SOR_EINVAL, "seg_rows must be even and in 8..1024");
+    nt.seg_rows = t->seg_rows;
+  }
+  c->tiling[p] = nt;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_get_tiling(const sor_ctx *c, int32_t bits, sor_tiling *t) {
+  if (!c || !t) return SOR_EINVAL;
+  const int p = prec_index(bits);
+  if (p < 0) return SOR_EINVAL;
+  *t = c->tiling[p];
+  return SOR_OK;
+}
+
+sor_status sor_solve_f64(sor_ctx *c, double *u, const double *bdy, const double *rhs,
+                         int32_t n, double omega, double tol, int64_t max_iters,
+                         int64_t check_every, void *stream, sor_result *out,
+                         double *max_hist) {
+  return solve_plain<double>(c, kF64, u, bdy, rhs, n, omega, tol, max_iters,
+                             check_every, stream, out, max_hist);
+}
+
+sor_status sor_solve_f32(sor_ctx *c, float *u, const float *bdy, const float *rhs,
+                         int32_t n, double omega, double tol, int64_t max_iters,
+                         int64_t check_every, void *stream, sor_result *out,
+                         double *max_hist) {
+  return solve_plain<float>(c, kF32, u, bdy, rhs, n, omega, tol, max_iters,
+                            check_every, stream, out, max_hist);
+}
+
+sor_status sor_residual_f64(sor_ctx *c, const double *u, const double *bdy,
+                            const double *rhs, int32_t n, double *r, double *stats,
+                            void *stream) {
+  sor_status st = check_common(c, u, bdy, rhs, n, 1.0);
+  if (st != SOR_OK) return st;
+  if (!stats) return fail(c, SOR_EINVAL, "stats must not be NULL");
+  if (r && !is_device_ptr(c, r)) return fail(c, SOR_EINVAL, "r is not a device pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const Layout L = make_layout(n, kF64);
+  const size_t bytes = (size_t)L.elems() * sizeof(double);
+  if ((st = ensure(c, kGridA64, bytes))) return st;
+  if (rhs && (st = ensure(c, kF64Buf, bytes))) return st;
+  if ((st = ensure(c, kPartials, (size_t)residual_partials(n) * 3 * sizeof(double)))) return st;
+  if ((st = ensure(c, kStats, 4 * sizeof(double)))) return st;
+  double *U = origin<double>(c, kGridA64, L);
+  double *F = rhs ? origin<double>(c, kF64Buf, L) : nullptr;
+  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, s));
+  double *dstats = (double *)c->bufs[kStats].p;
+  HIP_TRY(c, launch_residual(U, F, L.pitch, n, r, (double *)c->bufs[kPartials].p, dstats,
+                             nullptr, kF32, 0, 0, s));
+  HIP_TRY(c, hipMemcpyAsync(c->host_stats, dstats, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  for (int k = 0; k < 3; ++k) stats[k] = c->host_stats[k];
+  return SOR_OK;
+}
+
+sor_status sor_solve_mixed(sor_ctx *c, double *u, const double *bdy, const double *rhs,
+                           int32_t n, double omega, double rel_tol, int64_t max_outer,
+                           int32_t inner_bits, int64_t inner_iters, void *stream,
+                           sor_result *out, double *rel_hist) {
+  sor_status st = check_common(c, u, bdy, rhs, n, omega);
+  if (st != SOR_OK) return st;
+  if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
+  if (!(rel_tol >= 0.0)) return fail(c, SOR_EINVAL, "rel_tol must be >= 0");
+  if (max_outer < 0) return fail(c, SOR_EINVAL, "max_outer must be >= 0");
+  if (inner_bits != 32 && inner_bits != 16) return fail(c, SOR_EINVAL, "inner_bits must be 32 or 16");
+  if (inner_iters <= 0) inner_iters = 2 * (int64_t)n;
+  hipStream_t s = (hipStream_t)stream;
+  const int plo = inner_bits == 32 ? kF32 : kF16;
+  const Layout L = make_layout(n, kF64);
+  const Layout Llo = make_layout(n, plo);
+  const size_t b64 = (size_t)L.elems() * sizeof(double);
+  const size_t blo = (size_t)Llo.elems() * (size_t)prec_bytes(plo);
+  if ((st = ensure(c, kGridA64, b64))) return st;
+  if (rhs && (st = ensure(c, kF64Buf, b64))) return st;
+  if ((st = ensure(c, kGridA32, blo)) || (st = ensure(c, kGridB32, blo)) ||
+      (st = ensure(c, kLoRhs, blo)))
+    return st;
+  if ((st = ensure(c, kPartials, (size_t)residual_partials(n) * 3 * sizeof(double)))) return st;
+  if ((st = ensure(c, kStats, 4 * sizeof(double)))) return st;
+  double *U = origin<double>(c, kGridA64, L);
+  double *F = rhs ? origin<double>(c, kF64Buf, L) : nullptr;
+  char *EA = (char *)c->bufs[kGridA32].p + Llo.origin_off() * prec_bytes(plo);
+  char *EB = (char *)c->bufs[kGridB32].p + Llo.origin_off() * prec_bytes(plo);
+  char *R = (char *)c->bufs[kLoRhs].p + Llo.origin_off() * prec_bytes(plo);
+  double *dstats = (double *)c->bufs[kStats].p;
+  double *partials = (double *)c->bufs[kPartials].p;
+  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, s));
+  // The inner right-hand side grid has a zero ring; only its interior changes.
+  HIP_TRY(c, launch_fill_zero(plo, R, Llo.pitch, n, s));
+
+  *out = sor_result{};
+  const double h = 1.0 / (double)(n + 1);
+  const double target = plo == kF16 ? std::ldexp(h * h, 14) / 0.0737 : 1.0;
+  long long outer = 0, inner_total = 0, passes = 0;
+  double rel = NAN, last_corr = NAN;
+  sor_status result = SOR_NOT_CONVERGED;
+  for (;;) {
+    HIP_TRY(c, launch_residual(U, F, L.pitch, n, nullptr, partials, dstats, nullptr,
+                               plo, Llo.pitch, 0, s));
+    HIP_TRY(c, hipMemcpyAsync(c->host_stats, dstats, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const double sr = c->host_stats[0], sb = c->host_stats[1], rinf = c->host_stats[2];
+    rel = sb > 0.0 ? std::sqrt(sr) / std::sqrt(sb) : std::sqrt(sr);
+    if (rel_hist) rel_hist[outer] = rel;
+    if (!std::isfinite(rel)) { result = SOR_ENONFINITE; fail(c, result, "non-finite residual"); break; }
+    if (rel <= rel_tol || rinf == 0.0) { result = SOR_OK; break; }
+    if (outer == max_outer) break;
+    int e2;
+    std::frexp(target / rinf, &e2);
+    const int p = e2 - 1;
+    // r -> inner right-hand side, fl(r * 2^p).
+    HIP_TRY(c, launch_residual(U, F, L.pitch, n, nullptr, partials, dstats, R, plo,
+                               Llo.pitch, p, s));
+    HIP_TRY(c, launch_fill_zero(plo, EA, Llo.pitch, n, s));
+    HIP_TRY(c, launch_fill_zero(plo, EB, Llo.pitch, n, s));
+    // inner_iters sweeps, no stopping test (tol = 0 never passes).
+    const Sched sc{inner_iters, inner_iters, 0.0};
+    void *res_grid = EA;
+    sor_result ir{};
+    st = run_sweeps(c, plo, Llo, EA, EB, R, omega, sc, s, &ir, nullptr, &res_grid);
+    if (st == SOR_ENONFINITE) { result = st; break; }
+    if (st != SOR_NOT_CONVERGED && st != SOR_OK) return st;
+    inner_total += inner_iters;
+    passes += ir.passes;
+    unsigned long long *mb = (unsigned long long *)(dstats + 3);
+    HIP_TRY(c, hipMemsetAsync(mb, 0, sizeof(unsigned long long), s));
+    HIP_TRY(c, launch_accumulate(U, L.pitch, res_grid, plo, Llo.pitch, n, p, mb, s));
+    HIP_TRY(c, hipMemcpyAsync(c->host_stats + 3, mb, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    last_corr = c->host_stats[3];
+    ++outer;
+  }
+  HIP_TRY(c, launch_unpack(kF64, U, u, L.pitch, n, s));
+  HIP_TRY(c, hipStreamSynchronize(s));
+  out->iterations = inner_total;
+  out->final_max_delta = last_corr;
+  out->converged = result == SOR_OK;
+  out->outer_steps = (int32_t)outer;
+  out->rel_residual = rel;
+  out->passes = passes;
+  return result;
+}
+
+}  // extern "C"

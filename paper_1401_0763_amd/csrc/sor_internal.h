@@ -1,0 +1,124 @@
+// Internal declarations shared by the host runtime and the device code of
+// libsor.  Not part of the public ABI (include/sor.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sor {
+
+// ---------------------------------------------------------------------------
+// Padded working-grid layout (device memory owned by the library)
+//
+// A grid with n interior nodes per side is stored with its boundary ring
+// (rows/columns 0 and n+1) plus kMY margin rows above and below and kMX margin
+// columns on the left.  Element (r, c), -kMY <= r <= n+1+kMY and
+// -kMX <= c < pitch-kMX, lives at origin[r * pitch + c], where `origin` points
+// kMY rows and kMX columns into the allocation.  Rows start on 256-byte
+// boundaries.  Margin contents are never read into interior results.
+// ---------------------------------------------------------------------------
+constexpr int kMX = 16;           // left margin columns (>= widest halo)
+constexpr int kMY = 16;           // top and bottom margin rows (>= 2 * kTMax)
+constexpr int kTMax = 8;          // most iterations one blocked pass applies
+constexpr int kSlots = 64;        // partial-maximum slots per pass
+constexpr int kHistCap = 1024;    // per-iteration maxima kept per solve chunk
+constexpr int kLanes = 64;        // wavefront width on CDNA
+
+// Storage precisions.
+enum Prec : int { kF64 = 0, kF32 = 1, kF16 = 2 };
+
+inline int prec_bytes(int prec) { return prec == kF64 ? 8 : prec == kF32 ? 4 : 2; }
+// Cells held per lane by the blocked kernel (one 16-byte access for FP64 and
+// FP32, one 8-byte access for FP16 storage).
+inline int prec_cells(int prec) { return prec == kF64 ? 2 : 4; }
+
+struct Layout {
+  int32_t n = 0;
+  int64_t pitch = 0;    // elements per row
+  int64_t rows = 0;     // allocated rows (n + 2 + 2*kMY)
+  int64_t elems() const { return pitch * rows; }
+  int64_t origin_off() const { return (int64_t)kMY * pitch + kMX; }
+};
+Layout make_layout(int n, int prec);
+
+// Device-resident control block of one solve: partial maxima of the running
+// pass, pass bookkeeping and the stopping verdict (Algorithm 1's
+// shouldCheckConvergence / maxChange / hasConverged state).
+struct alignas(256) Ctl {
+  unsigned long long slots[kSlots][kTMax];  // bit patterns of non-negative doubles
+  unsigned int counter;     // wavefronts finished in the running pass
+  unsigned int nonfinite;   // sticky: a stored value was NaN or infinite
+  int stop;                 // 0 running, 1 converged, 2 non-finite
+  int pad0;
+  long long it_base;        // iterations completed by finished passes
+  long long stop_iter;      // iteration whose check passed
+  double stop_max;
+  long long last_iter;      // last checked iteration
+  double last_max;
+  long long passes_done;
+  double hist[kHistCap];    // change of iteration it at hist[(it-1) % kHistCap]
+};
+
+// Stopping schedule (Algorithm 1): check when it % check_every == 0 or
+// it == max_iters; converged when the change is strictly below tol.
+struct Sched {
+  long long max_iters;
+  long long check_every;
+  double tol;
+};
+
+// One grid as seen by the sweep kernels.
+struct GridView {
+  const void *in;       // origin of the input working grid
+  void *out;            // origin of the output working grid (may equal in for SIMPLE)
+  const void *F;        // origin of the source grid (h*h*f), or nullptr
+  int64_t pitch;
+  int32_t n;
+  int32_t nstrips;      // column strips of the blocked kernel
+  int32_t nseg;         // row segments of the blocked kernel
+  int32_t seg_rows;     // output rows per segment (even)
+  double omega;
+};
+
+// Geometry of the blocked kernel for a precision and iterations-per-pass T.
+struct BlockGeom {
+  int V, S, A, CW;
+};
+BlockGeom block_geom(int prec, int T);
+
+// ----------------------------- launchers ----------------------------------
+hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t s);
+hipError_t launch_pack(int prec, const void *u, const void *bdy, void *gridA,
+                       void *gridB, int64_t pitch, int n, hipStream_t s);
+hipError_t launch_pack_rhs(int prec, const void *f, void *F, int64_t pitch,
+                           int n, hipStream_t s);
+hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
+                         int n, hipStream_t s);
+hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
+                            hipStream_t s);
+// Blocked pass with the kernel built for T iterations (T in 1,2,3,4,6,8),
+// applying t_run <= T of them from v.in into v.out.  ctl == nullptr runs
+// without maxima, verdict or early exit.
+hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
+                               const Sched &sc, int t_run, hipStream_t s);
+bool blocked_T_supported(int T);
+// Simple kernel: one launch per colour, in place on v.in (v.out ignored).
+hipError_t launch_simple_iteration(int prec, const GridView &v, Ctl *ctl,
+                                   const Sched &sc, hipStream_t s);
+// FP64 residual.  partials: device scratch of residual_partials(n) * 3
+// doubles; stats: device double[3].  r (nullable): n*n output.  If lo_grid is
+// non-null, also writes fl(r * 2^scale_exp) into that padded low-precision
+// grid (prec_lo = kF32 or kF16).
+int64_t residual_partials(int n);
+hipError_t launch_residual(const double *U, const double *F, int64_t pitch,
+                           int n, double *r, double *partials, double *stats,
+                           void *lo_grid, int prec_lo, int64_t lo_pitch,
+                           int scale_exp, hipStream_t s);
+// U[interior] += (double)E * 2^-scale_exp; E is the low-precision grid.
+// maxabs (device double, may be null) receives max |(double)E * 2^-scale_exp|.
+hipError_t launch_accumulate(double *U, int64_t pitch, const void *E,
+                             int prec_lo, int64_t lo_pitch, int n,
+                             int scale_exp, unsigned long long *maxabs_bits,
+                             hipStream_t s);
+
+}  // namespace sor

@@ -1,0 +1,291 @@
+"""GPU parity: the HIP path against the CPU oracle on identical seeded inputs.
+
+FP64 and FP32 plain solves must agree with the oracle bit for bit (same
+update expression, no contraction, exact max) -- both the final grid and every
+iteration's max change -- and stop at the same iteration.  Mixed precision
+must agree bit for bit at a fixed number of corrections.  The residual must
+agree bit for bit per cell; its sums (different summation order) to 1e-12.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import (laplace_random_boundary, laplace_top_edge, omega_opt,
+                       poisson_manufactured, random_small)
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sor():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_1401_0763_amd as m
+    return m
+
+
+@pytest.fixture()
+def ctx(sor):
+    c = sor.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a, dtype=torch.float64):
+    return None if a is None else torch.tensor(np.ascontiguousarray(a), dtype=dtype,
+                                               device="cuda")
+
+
+def run_gpu(sor, ctx, g, tol, iters, K, dtype=torch.float64, hist=True):
+    u = dev(g.u0, dtype)
+    fn = sor.solve_f64 if dtype == torch.float64 else sor.solve_f32
+    res = fn(u, dev(g.bdy, dtype), dev(g.f, dtype), g.omega, tol, iters, K,
+             hist=hist, ctx=ctx)
+    return res, u.cpu().numpy()
+
+
+def assert_bitwise(a, b, what):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    if not np.array_equal(a.view(np.uint64 if a.dtype == np.float64 else np.uint32),
+                          b.view(np.uint64 if b.dtype == np.float64 else np.uint32)):
+        diff = np.abs(a.astype(np.float64) - b.astype(np.float64))
+        k = np.unravel_index(np.argmax(diff), diff.shape)
+        raise AssertionError(f"{what}: {np.count_nonzero(diff)} differ; max {diff.max()} at {k}")
+
+
+# ---------------------------------------------------------------------------
+# FP64, fixed iteration count, many tilings
+# ---------------------------------------------------------------------------
+
+TILINGS = [(1, 8), (2, 16), (3, 8), (4, 64), (6, 32), (8, 8), (8, 128)]
+
+
+@pytest.mark.parametrize("n,with_f,iters", [
+    (1, True, 7), (2, False, 9), (3, True, 13), (17, True, 31), (64, False, 40),
+    (100, True, 37), (255, True, 50), (300, False, 23)])
+def test_f64_fixed_iterations_bitwise_all_tilings(sor, ctx, n, with_f, iters):
+    g = random_small(1000 + n, n, with_f=with_f, nonzero_u0=True)
+    ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 0.0, iters, 1, hist=True)
+    for T, seg in TILINGS:
+        _say(f"f64 n={n} f={with_f} iters={iters} T={T} seg={seg}")
+        ctx.set_kernel(sor.KERNEL_BLOCKED)
+        ctx.set_tiling(64, T, seg)
+        res, u = run_gpu(sor, ctx, g, 0.0, iters, 1)
+        assert res.status == sor.NOT_CONVERGED and res.iterations == iters
+        assert_bitwise(u, ref.u, f"u n={n} T={T} seg={seg}")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} T={T}")
+    _say(f"f64 n={n} simple kernel")
+    ctx.set_kernel(sor.KERNEL_SIMPLE)
+    res, u = run_gpu(sor, ctx, g, 0.0, iters, 1)
+    assert_bitwise(u, ref.u, f"u n={n} simple")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} simple")
+
+
+def test_f64_laplace_top_edge_to_convergence_k1(sor, ctx):
+    """256x256 Laplace, north = 100, omega_opt, tol 1e-6 checked every iteration."""
+    g = laplace_top_edge(256)
+    ref = oracle.sor_f64(g.u0, g.bdy, None, g.omega, g.tol, g.max_iters, 1, hist=True)
+    assert ref.status == oracle.OK
+    for T, seg in [(4, 64), (3, 32), (8, 256)]:
+        _say(f"top edge 256 T={T} seg={seg}")
+        ctx.set_tiling(64, T, seg)
+        res, u = run_gpu(sor, ctx, g, g.tol, g.max_iters, 1)
+        assert res.status == sor.OK and res.converged
+        assert res.iterations == ref.iterations
+        assert res.final_max_delta == ref.final_max_delta
+        assert_bitwise(u, ref.u, "u")
+        assert_bitwise(np.array(res.hist), ref.mhist, "hist")
+
+
+@pytest.mark.parametrize("K,T", [(10, 4), (7, 3), (1, 8), (5, 6)])
+def test_f64_check_cadence_and_rollback(sor, ctx, K, T):
+    """Stops at the first checked iteration below tol, also inside a pass."""
+    n = 48
+    g = random_small(7, n, with_f=True)
+    full = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 0.0, 600, 1, hist=True)
+    for tol in (1e-3, 1e-6, 1e-9):
+        ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, tol, 600, K)
+        _say(f"cadence K={K} T={T} tol={tol} ref_it={ref.iterations}")
+        ctx.set_tiling(64, T, 16)
+        res, u = run_gpu(sor, ctx, g, tol, 600, K)
+        assert res.status == ref.status
+        assert res.iterations == ref.iterations
+        assert res.final_max_delta == ref.final_max_delta
+        assert_bitwise(u, ref.u, "u")
+        assert_bitwise(np.array(res.hist), full.mhist[: ref.iterations], "hist")
+
+
+@pytest.mark.parametrize("max_iters", [1, 5, 11, 1030])
+def test_f64_iteration_limit_not_multiple_of_pass(sor, ctx, max_iters):
+    n = 33
+    g = random_small(8, n, with_f=False)
+    ref = oracle.sor_f64(g.u0, g.bdy, None, g.omega, 0.0, max_iters, 4)
+    ctx.set_tiling(64, 6, 8)
+    res, u = run_gpu(sor, ctx, g, 0.0, max_iters, 4, hist=False)
+    assert res.status == sor.NOT_CONVERGED and res.iterations == max_iters
+    assert res.final_max_delta == ref.final_max_delta
+    assert_bitwise(u, ref.u, "u")
+
+
+def test_f64_underrelaxation_paper_omega(sor, ctx):
+    """The paper's omega = 0.376, north edge 1.0, others 0 (Sec. 2.1, 3.4)."""
+    n = 96
+    bdy = np.zeros(4 * n)
+    bdy[:n] = 1.0
+    ref = oracle.sor_f64(np.zeros((n, n)), bdy, None, 0.376, 1e-5, 400, 40, hist=True)
+    from workloads import Grid
+    g = Grid(n, np.zeros((n, n)), bdy, None, 0.376)
+    ctx.set_tiling(64, 4, 64)
+    res, u = run_gpu(sor, ctx, g, 1e-5, 400, 40)
+    assert res.iterations == ref.iterations and res.status == ref.status
+    assert_bitwise(u, ref.u, "u")
+
+
+def test_f64_nonfinite_boundary_reported(sor, ctx):
+    n = 20
+    g = random_small(9, n, with_f=False)
+    g.bdy[5] = np.nan
+    ref = oracle.sor_f64(g.u0, g.bdy, None, g.omega, 1e-6, 100, 1)
+    assert ref.status == oracle.ENONFINITE
+    for kernel in (sor.KERNEL_BLOCKED, sor.KERNEL_SIMPLE):
+        ctx.set_kernel(kernel)
+        res, _ = run_gpu(sor, ctx, g, 1e-6, 100, 1, hist=False)
+        assert res.status == sor.ENONFINITE
+
+
+def test_invalid_arguments_rejected(sor, ctx):
+    n = 8
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    b = torch.zeros(4 * n, dtype=torch.float64, device="cuda")
+    for kw in (dict(omega=0.0), dict(omega=2.0), dict(tol=float("nan")),
+               dict(max_iters=0), dict(check_every=0)):
+        args = dict(omega=1.5, tol=1e-6, max_iters=10, check_every=1)
+        args.update(kw)
+        with pytest.raises(sor.SorError) as e:
+            sor.solve_f64(u, b, None, ctx=ctx, **args)
+        assert e.value.status == sor.EINVAL
+    # host pointers are refused by the library, not dereferenced
+    import ctypes
+    hu = np.zeros((n, n))
+    hb = np.zeros(4 * n)
+    res = sor._Result()
+    st = ctx.lib.sor_solve_f64(ctx.handle, ctypes.c_void_p(hu.ctypes.data),
+                               ctypes.c_void_p(hb.ctypes.data), None, n, 1.5, 1e-6,
+                               10, 1, None, ctypes.byref(res), None)
+    assert st == sor.EINVAL
+    with pytest.raises(sor.SorError):
+        ctx.set_tiling(64, 5, 64)
+    with pytest.raises(sor.SorError):
+        ctx.set_tiling(64, 4, 7)
+
+
+# ---------------------------------------------------------------------------
+# FP32 storage
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,with_f", [(1, True), (5, False), (77, True), (260, True)])
+def test_f32_fixed_iterations_bitwise(sor, ctx, n, with_f):
+    g = random_small(2000 + n, n, with_f=with_f, nonzero_u0=True)
+    g.u0 = g.u0.astype(np.float32).astype(np.float64)
+    g.bdy = g.bdy.astype(np.float32).astype(np.float64)
+    if g.f is not None:
+        g.f = g.f.astype(np.float32).astype(np.float64)
+    ref = oracle.sor_f32(g.u0, g.bdy, g.f, g.omega, 0.0, 29, 1, hist=True)
+    for T, seg in [(1, 8), (4, 64), (8, 16)]:
+        _say(f"f32 n={n} T={T} seg={seg}")
+        ctx.set_kernel(sor.KERNEL_BLOCKED)
+        ctx.set_tiling(32, T, seg)
+        res, u = run_gpu(sor, ctx, g, 0.0, 29, 1, dtype=torch.float32)
+        assert_bitwise(u, ref.u, f"u f32 n={n} T={T}")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"hist f32 n={n} T={T}")
+    ctx.set_kernel(sor.KERNEL_SIMPLE)
+    res, u = run_gpu(sor, ctx, g, 0.0, 29, 1, dtype=torch.float32)
+    assert_bitwise(u, ref.u, f"u f32 n={n} simple")
+
+
+def test_f32_convergence_iteration_matches(sor, ctx):
+    g = random_small(31, 90, with_f=True)
+    g.bdy = g.bdy.astype(np.float32).astype(np.float64)
+    g.f = g.f.astype(np.float32).astype(np.float64)
+    ref = oracle.sor_f32(g.u0, g.bdy, g.f, g.omega, 1e-3, 5000, 3)
+    assert ref.status == oracle.OK
+    ctx.set_tiling(32, 4, 32)
+    res, u = run_gpu(sor, ctx, g, 1e-3, 5000, 3, dtype=torch.float32, hist=False)
+    assert res.iterations == ref.iterations and res.converged
+    assert_bitwise(u, ref.u, "u")
+
+
+# ---------------------------------------------------------------------------
+# FP64 residual and mixed precision
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,with_f", [(1, True), (9, False), (300, True)])
+def test_residual_bitwise_cells_and_sums(sor, ctx, n, with_f):
+    g = random_small(3000 + n, n, with_f=with_f, nonzero_u0=True)
+    r_ref, sr, sb, mr = oracle.residual_f64(g.u0, g.bdy, g.f)
+    r = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    s = sor.residual_f64(dev(g.u0), dev(g.bdy), dev(g.f), r=r, ctx=ctx)
+    assert_bitwise(r.cpu().numpy(), r_ref, "r")
+    assert abs(s[0] - sr) <= 1e-12 * sr and abs(s[1] - sb) <= 1e-12 * sb
+    assert s[2] == mr
+
+
+@pytest.mark.parametrize("bits,n,outer", [(32, 63, 3), (32, 200, 2), (16, 63, 3), (16, 130, 2)])
+def test_mixed_fixed_outer_steps_bitwise(sor, ctx, bits, n, outer):
+    g = poisson_manufactured(n, seed=40 + n)
+    inner = 2 * n
+    ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, outer, bits, inner)
+    for T, seg in [(4, 64), (3, 16)]:
+        _say(f"mixed bits={bits} n={n} T={T}")
+        ctx.set_kernel(sor.KERNEL_BLOCKED)
+        ctx.set_tiling(bits, T, seg)
+        u = dev(g.u0)
+        res = sor.solve_mixed(u, dev(g.bdy), dev(g.f), g.omega, 0.0, outer, bits,
+                              inner, hist=True, ctx=ctx)
+        assert res.outer_steps == outer == ref.outer_steps
+        assert_bitwise(u.cpu().numpy(), ref.u, f"u mixed{bits} n={n}")
+        np.testing.assert_allclose(res.hist, ref.relhist, rtol=1e-10)
+
+
+@pytest.mark.parametrize("bits,tol", [(32, 1e-12), (16, 1e-10)])
+def test_mixed_reaches_tolerance_like_oracle(sor, ctx, bits, tol):
+    n = 127
+    g = poisson_manufactured(n, seed=77)
+    ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, tol, 40, bits, 2 * n)
+    assert ref.converged
+    u = dev(g.u0)
+    res = sor.solve_mixed(u, dev(g.bdy), dev(g.f), g.omega, tol, 40, bits, 2 * n,
+                          ctx=ctx)
+    assert res.converged and res.outer_steps == ref.outer_steps
+    assert res.rel_residual <= tol
+    assert_bitwise(u.cpu().numpy(), ref.u, "u")
+
+
+# ---------------------------------------------------------------------------
+# The full-size workload, in the configuration the benchmark times
+# ---------------------------------------------------------------------------
+
+def test_f64_full_size_4096_fixed_iterations_bitwise(sor, ctx):
+    """4096^2 Laplace, random boundary in [0, 100], omega_opt, 200 iterations,
+    checked every 10: whole grid and per-iteration changes bit for bit."""
+    g = laplace_random_boundary(4096, seed=2)
+    iters = 200
+    _say("4096 oracle (threads)")
+    ref = oracle.sor_f64(g.u0, g.bdy, None, g.omega, 0.0, iters, 10,
+                         threads=min(16, os.cpu_count() or 1), hist=True)
+    _say("4096 gpu")
+    res, u = run_gpu(sor, ctx, g, 0.0, iters, 10)
+    assert res.iterations == iters
+    assert_bitwise(u, ref.u, "u 4096")
+    assert_bitwise(np.array(res.hist), ref.mhist, "hist 4096")
