@@ -12,6 +12,7 @@ import glob
 import os
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -36,13 +37,20 @@ def build(verbose: bool = False) -> str:
     objs = []
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
+    live = {os.path.basename(s) + ".o" for s in sources()}
+    for f in os.listdir(objdir):
+        if f not in live:
+            os.remove(os.path.join(objdir, f))
     procs = []
+    jobs = max(1, min(16, os.cpu_count() or 1))
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         lang = ["-x", "hip"]
         cmd = [HIPCC] + lang + [f for f in FLAGS if f not in ("-shared",)] + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
+        while sum(p.poll() is None for p, _ in procs) >= jobs:
+            time.sleep(0.05)
         procs.append((subprocess.Popen(cmd), src))
         objs.append(obj)
     bad = [src for p, src in procs if p.wait() != 0]

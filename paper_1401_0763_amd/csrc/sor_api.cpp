@@ -49,7 +49,7 @@ struct sor_ctx {
   int device = 0;
   std::string err;
   int kernel = SOR_KERNEL_BLOCKED;
-  sor_tiling tiling[3] = {{4, 64}, {4, 64}, {4, 64}};   // by Prec
+  sor_tiling tiling[3] = {{4, 192}, {4, 96}, {4, 96}};  // by Prec
   DevBuf bufs[kNumRoles];
   Ctl *host_ctl = nullptr;                             // pinned mirror
   double *host_stats = nullptr;                        // pinned [4]
@@ -148,6 +148,23 @@ GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *i
   return v;
 }
 
+// The deepest supported pass (1, 2, 3, 4 or 6 iterations) of at most
+// `left` iterations and at most T.
+int pass_depth(long long left, int T) {
+  static const int kDepths[] = {6, 4, 3, 2, 1};
+  for (int t : kDepths)
+    if (t <= T && t <= left) return t;
+  return 1;
+}
+
+GridView view_for(const GridView &base, int prec, int T) {
+  GridView v = base;
+  const BlockGeom g = block_geom(prec, T);
+  v.nstrips = (v.n + 1 + g.CW - 1) / g.CW;
+  v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
+  return v;
+}
+
 struct PassRec {
   const void *in;
   void *out;
@@ -195,8 +212,8 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
     recs.clear();
     // Enqueue up to `chunk` passes (a truncated pass when < T iterations remain).
     for (long long k = 0; k < chunk && done < sc.max_iters; ++k) {
-      const int Tp = (int)std::min<long long>(T, sc.max_iters - done);
-      GridView v = base;
+      const int Tp = pass_depth(sc.max_iters - done, T);
+      GridView v = simple ? base : view_for(base, prec, Tp);
       v.in = cur;
       v.out = simple ? cur : oth;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -208,7 +225,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       if (simple) {
         HIP_TRY(c, launch_simple_iteration(prec, v, ctl, sc, s));
       } else {
-        HIP_TRY(c, launch_blocked_pass(prec, T, v, ctl, sc, Tp, s));
+        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s));
         std::swap(cur, oth);
       }
       if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
@@ -250,15 +267,23 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       if (h.stop_iter == pr->it0 + pr->T || simple) {
         *result_grid = pr->out;
       } else {
-        // Rule met inside the pass: redo it from its intact input.
-        GridView v = base;
-        v.in = pr->in;
-        v.out = pr->out;
-        const int Tr = (int)(h.stop_iter - pr->it0);
-        HIP_TRY(c, launch_blocked_pass(prec, T, v, nullptr, sc, Tr, s));
-        ++reruns;
+        // Rule met inside the pass: redo its first iterations from its intact
+        // input, ping-ponging between the pass's two grids.
+        void *src = const_cast<void *>(pr->in);
+        void *dst = pr->out;
+        long long left = h.stop_iter - pr->it0;
+        while (left > 0) {
+          const int t = pass_depth(left, T);
+          GridView v = view_for(base, prec, t);
+          v.in = src;
+          v.out = dst;
+          HIP_TRY(c, launch_blocked_pass(prec, t, v, nullptr, sc, s));
+          ++reruns;
+          *result_grid = dst;
+          std::swap(src, dst);
+          left -= t;
+        }
         res->passes = h.passes_done + reruns;
-        *result_grid = pr->out;
       }
       return SOR_OK;
     }
@@ -388,7 +413,7 @@ sor_status sor_ctx_set_tiling(sor_ctx *c, int32_t bits, const sor_tiling *t) {
   sor_tiling nt = c->tiling[p];
   if (t->iters_per_pass) {
     if (!blocked_T_supported(t->iters_per_pass))
-      return fail(c, SOR_EINVAL, "iters_per_pass must be 1, 2, 3, 4, 6 or 8");
+      return fail(c, SOR_EINVAL, "iters_per_pass must be 1, 2, 3, 4 or 6");
     nt.iters_per_pass = t->iters_per_pass;
   }
   if (t->seg_rows) {

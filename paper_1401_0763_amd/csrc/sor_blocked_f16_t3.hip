@@ -1,0 +1,7 @@
+// Blocked red-black SOR pass, binary16 storage, 3 iteration(s) per pass.
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF16, 3>(const GridView &, Ctl *,
+                                              const Sched &, hipStream_t);
+}  // namespace sor

@@ -320,23 +320,40 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_blocked_f64(int T, const GridView &v, Ctl *ctl, const Sched &sc,
-                              int t_run, hipStream_t s);
-hipError_t launch_blocked_f32(int T, const GridView &v, Ctl *ctl, const Sched &sc,
-                              int t_run, hipStream_t s);
-hipError_t launch_blocked_f16(int T, const GridView &v, Ctl *ctl, const Sched &sc,
-                              int t_run, hipStream_t s);
+// The blocked passes are instantiated in the sor_blocked_*_t*.hip units.
+#define SOR_EXTERN_BLOCKED(P, T)                                               \
+  extern template hipError_t launch_blocked_PT<P, T>(                          \
+      const GridView &, Ctl *, const Sched &, hipStream_t);
+#define SOR_EXTERN_BLOCKED_ALL(P)                                              \
+  SOR_EXTERN_BLOCKED(P, 1) SOR_EXTERN_BLOCKED(P, 2) SOR_EXTERN_BLOCKED(P, 3)   \
+  SOR_EXTERN_BLOCKED(P, 4) SOR_EXTERN_BLOCKED(P, 6)
+SOR_EXTERN_BLOCKED_ALL(kF64)
+SOR_EXTERN_BLOCKED_ALL(kF32)
+SOR_EXTERN_BLOCKED_ALL(kF16)
+
+template <int P>
+static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
+                                   const Sched &sc, hipStream_t s) {
+  switch (T) {
+    case 1: return launch_blocked_PT<P, 1>(v, ctl, sc, s);
+    case 2: return launch_blocked_PT<P, 2>(v, ctl, sc, s);
+    case 3: return launch_blocked_PT<P, 3>(v, ctl, sc, s);
+    case 4: return launch_blocked_PT<P, 4>(v, ctl, sc, s);
+    case 6: return launch_blocked_PT<P, 6>(v, ctl, sc, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 bool blocked_T_supported(int T) {
-  return T == 1 || T == 2 || T == 3 || T == 4 || T == 6 || T == 8;
+  return T == 1 || T == 2 || T == 3 || T == 4 || T == 6;
 }
 
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, int t_run, hipStream_t s) {
+                               const Sched &sc, hipStream_t s) {
   switch (prec) {
-    case kF64: return launch_blocked_f64(T, v, ctl, sc, t_run, s);
-    case kF32: return launch_blocked_f32(T, v, ctl, sc, t_run, s);
-    case kF16: return launch_blocked_f16(T, v, ctl, sc, t_run, s);
+    case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s);
+    case kF32: return launch_blocked_P<kF32>(T, v, ctl, sc, s);
+    case kF16: return launch_blocked_P<kF16>(T, v, ctl, sc, s);
   }
   return hipErrorInvalidValue;
 }

@@ -96,11 +96,11 @@ hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
                          int n, hipStream_t s);
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
-// Blocked pass with the kernel built for T iterations (T in 1,2,3,4,6,8),
-// applying t_run <= T of them from v.in into v.out.  ctl == nullptr runs
-// without maxima, verdict or early exit.
+// Blocked pass of T iterations (T in 1,2,3,4,6) from v.in into v.out; the
+// view's nstrips/nseg must match T.  ctl == nullptr runs without maxima,
+// verdict or early exit.
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, int t_run, hipStream_t s);
+                               const Sched &sc, hipStream_t s);
 bool blocked_T_supported(int T);
 // Simple kernel: one launch per colour, in place on v.in (v.out ignored).
 hipError_t launch_simple_iteration(int prec, const GridView &v, Ctl *ctl,

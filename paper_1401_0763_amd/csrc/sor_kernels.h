@@ -10,6 +10,17 @@
 
 #include "sor_internal.h"
 
+#include <type_traits>
+
+// Rows a wavefront loads ahead of the row it is updating.
+#ifndef SOR_PREFETCH
+#define SOR_PREFETCH 4
+#endif
+// Register-window periods unrolled per loop iteration of the row walk.
+#ifndef SOR_UNROLL
+#define SOR_UNROLL 1
+#endif
+
 namespace sor {
 
 // ---------------------------------------------------------------------------
@@ -24,6 +35,17 @@ template <int P>
 struct alignas(sizeof(typename PT<P>::st) * PT<P>::V) Vec {
   typename PT<P>::st v[PT<P>::V];
 };
+
+// Compile-time loop: calls f(std::integral_constant<int, I>) for I = B..E-1.
+// Used where an index selects a register (window slot, stage), so the index
+// must be a constant however large the unrolled body grows.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Cross-lane moves.  DPP wave_shr:1 hands every lane the value of the lane
@@ -149,6 +171,44 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access.  A buffer resource (base, byte extent) lives in SGPRs;
+// each access adds a per-lane VGPR offset and a wave-uniform SGPR offset.  A
+// store whose per-lane offset has bit 31 set lies beyond the resource's
+// extent (which is kept below 2^31) and is dropped by the hardware, which
+// gives predicated stores without a branch.
+// ---------------------------------------------------------------------------
+constexpr unsigned kDrop = 0x80000000u;
+constexpr unsigned kRsrcWord3 = 0x00020000u;   // gfx9 raw buffer, 32-bit format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base,
+                                                             unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes,
+                                           (int)kRsrcWord3);
+}
+
+template <int P>
+__device__ __forceinline__ Vec<P> buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                           unsigned soff) {
+  if constexpr (sizeof(Vec<P>) == 16) {
+    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  } else {
+    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_t r,
+                                          unsigned voff, unsigned soff) {
+  if constexpr (sizeof(Vec<P>) == 16) {
+    using v4 = unsigned __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4, x), r, (int)voff, (int)soff, 0);
+  } else {
+    using v2 = unsigned __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, x), r, (int)voff, (int)soff, 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Temporally blocked streaming sweep of one tile by one wavefront.
 //
 // The tile is a column strip of 64*V cells (V per lane, so one 16-byte access
@@ -170,20 +230,21 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
 // output are separate grids (ping-pong), so halos are read at the pass's
 // starting level whatever order tiles run in.
 //
-// Only the first 2*t_run stages are applied (t_run <= T iterations); the
-// rest leave the rows untouched, which lets one kernel finish a solve whose
-// iteration budget is not a multiple of T.
-//
-// Boundary and out-of-grid cells are never changed: their update is computed
-// and discarded by a select, so the unrolled body has no branches.
+// The step loop runs in chunks of W steps with no branch inside a chunk, so
+// the compiler can overlap the stages of neighbouring steps: loads read a
+// clamped row (always inside the tile's rows), stores of rows outside the
+// core are dropped by an out-of-range offset, and the per-iteration maxima
+// weight each change by 1 (core row) or 0 (halo row).  MASK tiles touch the
+// boundary ring or lie partly outside the grid; their boundary and
+// out-of-grid cells keep their value through a select.  Other tiles hold
+// interior cells only and need no mask.
 //
 // m[t] receives the largest |u' - u| of iteration t over the tile's core
 // cells (0 in halo lanes); bad is set if a stored interior value is not
 // finite.
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS>
+template <int P, int T, bool POIS, bool MASK>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
-                                             int t_run,
                                              typename PT<P>::ct (&m)[T],
                                              bool &bad) {
   using st = typename PT<P>::st;
@@ -193,32 +254,37 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   constexpr int A = ((S + V - 1) / V) * V;
   constexpr int WV = kLanes * V;
   constexpr int CW = WV - 2 * A;
-  constexpr int D = 2;                           // rows prefetched ahead
+  constexpr int D = SOR_PREFETCH;                // rows prefetched ahead
   constexpr int W = ((S + D + 2) + 1) & ~1;      // window rows (even)
+  constexpr int ESZ = (int)sizeof(st);
 
   const int lane = threadIdx.x & 63;
   const int n = g.n;
   const int strip = tile % g.nstrips;
   const int seg = tile / g.nstrips;
-  const int col0 = strip * CW - A + lane * V;    // even: parity below is static
+  const int j0 = strip * CW - A;                 // first column of the strip
+  const int col0 = j0 + lane * V;                // even: parity below is static
   const int a = seg * g.seg_rows - S;            // first loaded row (even)
   const int core0 = seg * g.seg_rows;
   const int core1 = min(core0 + g.seg_rows, n + 1);
   const int b = core1 + S;                       // one past the last loaded row
   const int rlo = max(core0, 1);
   const int rhi = min(core1, n + 1);
-  const int s_run = 2 * t_run;
   const bool lane_core = (lane * V >= A) && (lane * V < WV - A);
   const bool lane_store = lane_core && (col0 <= n) && (col0 + V - 1 >= 1);
   bool ok[V];
 #pragma unroll
   for (int v = 0; v < V; ++v) ok[v] = (col0 + v >= 1) && (col0 + v <= n);
   const ct om = (ct)g.omega;
-  const int64_t pitch = g.pitch;
-  const st *in = (const st *)g.in + col0;
-  st *out = (st *)g.out + col0;
-  const st *F = nullptr;
-  if constexpr (POIS) F = (const st *)g.F + col0;
+  const unsigned rowbytes = (unsigned)(g.pitch * ESZ);
+  const unsigned extent = (unsigned)(b - a) * rowbytes;     // < 2^31
+  const int64_t tile_off = (int64_t)a * g.pitch + j0;
+  const auto rin = make_rsrc((const st *)g.in + tile_off, extent);
+  const auto rout = make_rsrc((st *)g.out + tile_off, extent);
+  __amdgpu_buffer_rsrc_t rf;
+  if constexpr (POIS) rf = make_rsrc((const st *)g.F + tile_off, extent);
+  const unsigned lane_off = (unsigned)(lane * V * ESZ);
+  const unsigned st_off = lane_store ? lane_off : kDrop;
 
   ct w[W][V];
   ct fw[POIS ? W : 1][V];
@@ -235,80 +301,84 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   // Prologue: rows a .. a+D+1 into slots 0 .. D+1 (b - a >= 2S + 1 > D + 2).
 #pragma unroll
   for (int s = 0; s < D + 2; ++s) {
-    const Vec<P> x = *(const Vec<P> *)(in + (int64_t)(a + s) * pitch);
+    const Vec<P> x = buf_load<P>(rin, lane_off, (unsigned)s * rowbytes);
 #pragma unroll
     for (int v = 0; v < V; ++v) w[s][v] = (ct)x.v[v];
     if constexpr (POIS) {
-      const Vec<P> y = *(const Vec<P> *)(F + (int64_t)(a + s) * pitch);
+      const Vec<P> y = buf_load<P>(rf, lane_off, (unsigned)s * rowbytes);
 #pragma unroll
       for (int v = 0; v < V; ++v) fw[s][v] = (ct)y.v[v];
     }
   }
 
   const int nsteps = b - a - 2;                  // steps r = a+1 .. b-2
-  for (int base = 0; base < nsteps; base += W) {
+  constexpr int CH = W * SOR_UNROLL;             // steps per loop iteration
+  for (int base = 0; base < nsteps; base += CH) {
+    static_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+      constexpr int i = decltype(I)::value;
+      const int r = a + 1 + base + i;
+      // Prefetch row r+D+1 (clamped to the tile) into its slot ((row-a) mod W).
+      {
+        constexpr int sp = (i + D + 2) % W;
+        const int rp = min(r + D + 1, b - 1);
+        const unsigned soff = (unsigned)(rp - a) * rowbytes;
+        const Vec<P> x = buf_load<P>(rin, lane_off, soff);
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      const int step = base + i;
-      if (step < nsteps) {
-        const int r = a + 1 + step;
-        // Prefetch row r+D+1 into its slot ((row - a) mod W).
-        const int rp = r + D + 1;
-        if (rp < b) {
-          const int sp = (i + D + 2) % W;
-          const Vec<P> x = *(const Vec<P> *)(in + (int64_t)rp * pitch);
+        for (int v = 0; v < V; ++v) w[sp][v] = (ct)x.v[v];
+        if constexpr (POIS) {
+          const Vec<P> y = buf_load<P>(rf, lane_off, soff);
 #pragma unroll
-          for (int v = 0; v < V; ++v) w[sp][v] = (ct)x.v[v];
-          if constexpr (POIS) {
-            const Vec<P> y = *(const Vec<P> *)(F + (int64_t)rp * pitch);
-#pragma unroll
-            for (int v = 0; v < V; ++v) fw[sp][v] = (ct)y.v[v];
-          }
-        }
-        // Stages: k-th half-sweep on row r-k.
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-          const int q = r - k;
-          const bool row_upd = (q >= 1) && (q <= n) && (k < s_run);   // uniform
-          const bool row_cnt = (q >= rlo) && (q < rhi);                // uniform
-          const int sq = ((i + 1 - k) % W + W) % W;
-          const int su = (sq + W - 1) % W;
-          const int sd = (sq + 1) % W;
-          // Cells of colour k&1 in this lane: (q + col0 + v + k) even, and
-          // q + k has the parity of 1 + i because a, base and W are even.
-          const int v0 = (1 + i) & 1;
-#pragma unroll
-          for (int v = v0; v < V; v += 2) {
-            const ct self = w[sq][v];
-            const ct left = (v == 0) ? from_left(w[sq][V - 1]) : w[sq][(v + V - 1) % V];
-            const ct right = (v == V - 1) ? from_right(w[sq][0]) : w[sq][(v + 1) % V];
-            ct s = (w[su][v] + w[sd][v]) + (left + right);
-            if constexpr (POIS) s = s + fw[sq][v];
-            const ct gs = (ct)0.25 * s;
-            ct nu = self + om * (gs - self);
-            if constexpr (P == kF16) nu = (ct)(st)nu;
-            nu = (row_upd && ok[v]) ? nu : self;
-            const ct d = vabs(nu - self);
-            w[sq][v] = nu;
-            m[k >> 1] = vmax(m[k >> 1], row_cnt ? d : (ct)0);
-          }
-        }
-        // Row r-S+1 has now had all S half-sweeps: store it if it is core.
-        const int qo = r - S + 1;
-        if (qo >= rlo && qo < rhi) {
-          const int so = ((i + 2 - S) % W + W) % W;
-          if (lane_store) {
-            Vec<P> x;
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-              x.v[v] = (st)w[so][v];
-              if (ok[v] && !__builtin_isfinite(w[so][v])) bad = true;
-            }
-            *(Vec<P> *)(out + (int64_t)qo * pitch) = x;
-          }
+          for (int v = 0; v < V; ++v) fw[sp][v] = (ct)y.v[v];
         }
       }
-    }
+      // Stages: k-th half-sweep on row r-k.
+      static_for<0, S>([&](auto K) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        constexpr int sq = ((i + 1 - k) % W + W) % W;
+        constexpr int su = (sq + W - 1) % W;
+        constexpr int sd = (sq + 1) % W;
+        // Cells of colour k&1 in this lane: (q + col0 + v + k) even, and
+        // q + k has the parity of 1 + i because a, base and W are even.
+        constexpr int v0 = (1 + i) & 1;
+        const int q = r - k;
+        const ct cnt = (q >= rlo && q < rhi) ? (ct)1 : (ct)0;        // uniform
+        const bool row_upd = (q >= 1) && (q <= n);                   // uniform
+        static_for<0, V / 2>([&](auto J) __attribute__((always_inline)) {
+          constexpr int v = v0 + 2 * decltype(J)::value;
+          const ct self = w[sq][v];
+          ct left, right;
+          if constexpr (v == 0) left = from_left(w[sq][V - 1]);
+          else left = w[sq][v - 1];
+          if constexpr (v == V - 1) right = from_right(w[sq][0]);
+          else right = w[sq][v + 1];
+          ct s = (w[su][v] + w[sd][v]) + (left + right);
+          if constexpr (POIS) s = s + fw[sq][v];
+          const ct gs = (ct)0.25 * s;
+          ct nu = self + om * (gs - self);
+          if constexpr (P == kF16) nu = (ct)(st)nu;
+          if constexpr (MASK) nu = (row_upd && ok[v]) ? nu : self;
+          const ct d = vabs(nu - self);
+          w[sq][v] = nu;
+          m[k >> 1] = vmax(m[k >> 1], d * cnt);
+        });
+      });
+      // Row r-S+1 has now had all S half-sweeps: store it if it is core.
+      {
+        constexpr int so = ((i + 2 - S) % W + W) % W;
+        const int qo = r - S + 1;
+        const bool row_ok = (qo >= rlo) && (qo < rhi);
+        Vec<P> x;
+        bool nf = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          x.v[v] = (st)w[so][v];
+          nf = nf | (ok[v] && !__builtin_isfinite(w[so][v]));
+        }
+        bad = bad | (nf && row_ok && lane_store);
+        buf_store<P>(x, rout, st_off | (row_ok ? 0u : kDrop),
+                     row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
+      }
+    });
   }
   if (!lane_core) {
 #pragma unroll
@@ -316,51 +386,53 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   }
 }
 
-// One blocked pass over a whole grid: one wavefront per tile, t_run <= T
-// iterations from g.in into g.out.  With a control block, the pass first
-// exits if an earlier pass met the stopping rule, then reports its maxima.
+// One blocked pass over a whole grid: one wavefront per tile, T iterations
+// from g.in into g.out.  With a control block, the pass first exits if an
+// earlier pass met the stopping rule, then reports its maxima.
 template <int P, int T, bool POIS>
 __global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
-                                                          Sched sc, int t_run) {
+                                                          Sched sc) {
   if (ctl && ctl_stopped(ctl)) return;
   using ct = typename PT<P>::ct;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  constexpr int V = PT<P>::V;
+  constexpr int S = 2 * T;
+  constexpr int A = ((S + V - 1) / V) * V;
+  constexpr int CW = kLanes * V - 2 * A;
+  // A tile needs masking if its loaded rows or columns reach the boundary
+  // ring or beyond (rows a..b-1, columns j0..j0+64V-1).
+  const int strip = tile % g.nstrips, seg = tile / g.nstrips;
+  const int j0 = strip * CW - A;
+  const int a = seg * g.seg_rows - S;
+  const int b = min(a + S + g.seg_rows, g.n + 1) + S;
+  const bool mask = (j0 < 1) || (j0 + kLanes * V - 1 > g.n) || (a < 1) || (b - 1 > g.n);
   ct m[T];
   bool bad = false;
-  blocked_tile<P, T, POIS>(g, tile, t_run, m, bad);
+  if (mask)
+    blocked_tile<P, T, POIS, true>(g, tile, m, bad);
+  else
+    blocked_tile<P, T, POIS, false>(g, tile, m, bad);
   if (!ctl) return;
   double mx[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
-  report_pass<T>(ctl, sc, mx, t_run, bad, blockIdx.x % kSlots, gridDim.x);
+  report_pass<T>(ctl, sc, mx, T, bad, blockIdx.x % kSlots, gridDim.x);
 }
 
-// Host-side dispatch of blocked passes for one precision (defined in the
-// per-precision translation units).
-#define SOR_BLOCKED_LAUNCHER(P, NAME)                                          \
-  template <int T>                                                             \
-  static void NAME##_T(const GridView &v, Ctl *ctl, const Sched &sc,           \
-                       int t_run, hipStream_t s) {                             \
-    const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);                   \
-    if (v.F)                                                                   \
-      hipLaunchKernelGGL((blocked_pass_kernel<P, T, true>), grid, dim3(64), 0, \
-                         s, v, ctl, sc, t_run);                                \
-    else                                                                       \
-      hipLaunchKernelGGL((blocked_pass_kernel<P, T, false>), grid, dim3(64),   \
-                         0, s, v, ctl, sc, t_run);                             \
-  }                                                                            \
-  hipError_t NAME(int T, const GridView &v, Ctl *ctl, const Sched &sc,         \
-                  int t_run, hipStream_t s) {                                  \
-    switch (T) {                                                               \
-      case 1: NAME##_T<1>(v, ctl, sc, t_run, s); break;                        \
-      case 2: NAME##_T<2>(v, ctl, sc, t_run, s); break;                        \
-      case 3: NAME##_T<3>(v, ctl, sc, t_run, s); break;                        \
-      case 4: NAME##_T<4>(v, ctl, sc, t_run, s); break;                        \
-      case 6: NAME##_T<6>(v, ctl, sc, t_run, s); break;                        \
-      case 8: NAME##_T<8>(v, ctl, sc, t_run, s); break;                        \
-      default: return hipErrorInvalidValue;                                    \
-    }                                                                          \
-    return hipGetLastError();                                                  \
-  }
+// Host-side launch of the blocked pass for one (precision, T); each pair is
+// instantiated in its own translation unit so the unrolled bodies compile in
+// parallel.
+template <int P, int T>
+hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
+                             hipStream_t s) {
+  const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
+  if (v.F)
+    hipLaunchKernelGGL((blocked_pass_kernel<P, T, true>), grid, dim3(64), 0, s,
+                       v, ctl, sc);
+  else
+    hipLaunchKernelGGL((blocked_pass_kernel<P, T, false>), grid, dim3(64), 0, s,
+                       v, ctl, sc);
+  return hipGetLastError();
+}
 
 }  // namespace sor
