@@ -24,6 +24,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blocked_pass_f64_4096.traffic.json")
+KERNEL_SOURCES = ("paper_1401_0763_amd/csrc/sor_kernels.h",
+                  "paper_1401_0763_amd/csrc/sor_internal.h",
+                  "paper_1401_0763_amd/build.py")
+
+
+def kernel_source_digest():
+    """Digest of the sources the blocked sweep kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n, T, seg):
+    """Counter-measured bytes per launch, if taken on the current kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("source_digest") != kernel_source_digest():
+        return None
+    if d.get("config") != {"n": n, "iters_per_pass": T, "seg_rows": seg}:
+        return None
+    return d["traffic_bytes_per_launch"]
 BYTES_PER_LUP_F64 = 16.0       # read u once + write u once per iteration
 
 
@@ -61,6 +89,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, run one device-to-device copy of this "
+                         "many MiB (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -87,6 +118,15 @@ def main():
 
     def step():
         return sor.solve_f64(u, bdy, None, g.omega, 0.0, iters, K, ctx=ctx)
+
+    if args.copy_probe_mib:
+        nel = args.copy_probe_mib * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -126,7 +166,8 @@ def main():
                    "iters_per_pass": T, "seg_rows": seg},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(n, T, seg),
                      "kernel": "blocked_pass_kernel<f64>",
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches": launches,
