@@ -74,6 +74,9 @@ typedef struct sor_result {
     int32_t outer_steps;      /* mixed: corrections applied; plain: 0        */
     double rel_residual;      /* mixed: final ||r||_2 / ||b||_2; plain: NaN  */
     int64_t passes;           /* sweep kernel passes that did work           */
+    int32_t status;           /* this solve's sor_status (batched solves
+                                 report one per grid)                         */
+    int32_t reserved;
 } sor_result;
 
 /* Library version string, e.g. "sor 0.1.0 gfx950". */
@@ -184,6 +187,55 @@ sor_status sor_solve_mixed(sor_ctx *ctx, double *u, const double *boundary,
                            double rel_tol, int64_t max_outer, int32_t inner_bits,
                            int64_t inner_iters, void *stream, sor_result *out,
                            double *rel_hist);
+
+/*
+ * One grid of a batched solve.  Arrays follow the conventions above (device
+ * pointers, caller-owned); each grid has its own size, omega, tolerance,
+ * check cadence and iteration limit.
+ */
+typedef struct sor_grid_desc {
+    double *u;                /* n*n interior: in initial guess, out result  */
+    const double *boundary;   /* 4n edge values (north, south, west, east)   */
+    const double *rhs;        /* n*n source f, or NULL for Laplace           */
+    int32_t n;
+    int32_t reserved;
+    double omega;             /* in (0, 2)                                   */
+    double tol;               /* stop when a checked change is < tol         */
+    int64_t max_iters;        /* >= 1                                        */
+    int64_t check_every;      /* >= 1                                        */
+} sor_grid_desc;
+
+/*
+ * Batched FP64 red-black SOR: every grid follows exactly the method of
+ * sor_solve_f64 (Sec. 2.1 Eq. 1, Sec. 3.1, Algorithm 1) and gets the result
+ * sor_solve_f64 would give it alone, bit for bit.  All grids advance together
+ * in one persistent kernel launch: each 64-lane wavefront repeatedly takes a
+ * (grid, tile) work item of some grid's current pass from a device queue; the
+ * wavefront that completes a grid's pass evaluates that grid's stopping rule
+ * and queues its next pass.  The launch sequence (uploads, packing, the
+ * persistent kernel, unpacking, result download) is recorded once as a HIP
+ * graph and replayed for later batches with the same shapes.
+ *   grids    HOST array of `count` descriptors (count >= 1)
+ *   results  HOST array of `count` results (status per grid in ->status)
+ * Tiles per grid come from the context's tuning table (sor_autotune) or a
+ * size-based default.  Returns SOR_OK when every grid converged,
+ * SOR_NOT_CONVERGED when some reached their limit, SOR_ENONFINITE when some
+ * produced a non-finite value, SOR_ETIMEOUT if a device-side queue wait
+ * exceeded its bound, or an argument / device error.
+ */
+sor_status sor_batch_solve_f64(sor_ctx *ctx, const sor_grid_desc *grids,
+                               int32_t count, void *stream, sor_result *results);
+
+/*
+ * Tiling autotuner: times blocked passes of every candidate tiling
+ * (iterations per pass x rows per tile) on a scratch n x n grid of the given
+ * storage precision (64 or 32 bits) with HIP events, stores the fastest in
+ * the context's tuning table for n's size class (side rounded to the nearest
+ * half power of two), and returns it in *best (may be NULL).  Later plain and
+ * batched solves of that precision and class use it.  Only timing is
+ * measured: results never depend on the tiling.
+ */
+sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best);
 
 #ifdef __cplusplus
 }

@@ -40,7 +40,17 @@ class _Result(ctypes.Structure):
                 ("converged", ctypes.c_int32),
                 ("outer_steps", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double),
-                ("passes", ctypes.c_int64)]
+                ("passes", ctypes.c_int64),
+                ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _GridDesc(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("boundary", ctypes.c_void_p),
+                ("rhs", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iters", ctypes.c_int64),
+                ("check_every", ctypes.c_int64)]
 
 
 class _Tiling(ctypes.Structure):
@@ -94,6 +104,11 @@ def _declare(lib):
     lib.sor_solve_mixed.argtypes = [P, P, P, P, i32, dbl, dbl, i64, i32, i64, P,
                                     ctypes.POINTER(_Result), P]
     lib.sor_solve_mixed.restype = ctypes.c_int
+    lib.sor_batch_solve_f64.argtypes = [P, ctypes.POINTER(_GridDesc), i32, P,
+                                        ctypes.POINTER(_Result)]
+    lib.sor_batch_solve_f64.restype = ctypes.c_int
+    lib.sor_autotune.argtypes = [P, i32, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_autotune.restype = ctypes.c_int
 
 
 def load_library():
@@ -164,6 +179,13 @@ class Context:
         t = _Tiling(int(iters_per_pass), int(seg_rows))
         self._check(self.lib.sor_ctx_set_tiling(self.handle, int(bits), ctypes.byref(t)))
 
+    def autotune(self, bits: int, n: int) -> tuple[int, int]:
+        """Time candidate tilings for an n x n grid; returns (iters_per_pass,
+        seg_rows) and records it for n's size class."""
+        t = _Tiling()
+        self._check(self.lib.sor_autotune(self.handle, int(bits), int(n), ctypes.byref(t)))
+        return t.iters_per_pass, t.seg_rows
+
     def get_tiling(self, bits: int) -> tuple[int, int]:
         t = _Tiling()
         self._check(self.lib.sor_ctx_get_tiling(self.handle, int(bits), ctypes.byref(t)))
@@ -210,6 +232,44 @@ def _check_tensor(name, t, dtype, shape):
 def _result(st, r: _Result, hist=None) -> Result:
     return Result(st, r.iterations, r.final_max_delta, bool(r.converged),
                   r.outer_steps, r.rel_residual, r.passes, hist)
+
+
+@dataclass
+class GridSpec:
+    """One grid of a batched solve (torch float64 CUDA tensors)."""
+    u: object                 # n x n, solved in place
+    boundary: object          # 4n
+    rhs: object = None        # n x n or None
+    omega: float | None = None
+    tol: float = 1e-8
+    max_iters: int = 1000000
+    check_every: int = 1
+
+
+def batch_solve_f64(specs, ctx: Context | None = None) -> list[Result]:
+    """Solve many grids in one persistent launch; one Result per grid."""
+    import torch
+    specs = list(specs)
+    if not specs:
+        return []
+    ctx = ctx or context(specs[0].u.device.index)
+    descs = (_GridDesc * len(specs))()
+    for k, sp in enumerate(specs):
+        n = sp.u.shape[0]
+        d = descs[k]
+        d.u = _check_tensor("u", sp.u, torch.float64, (n, n))
+        d.boundary = _check_tensor("boundary", sp.boundary, torch.float64, (4 * n,))
+        d.rhs = None if sp.rhs is None else _check_tensor("rhs", sp.rhs, torch.float64, (n, n))
+        d.n = n
+        d.omega = (2.0 / (1.0 + math.sin(math.pi / (n + 1)))) if sp.omega is None else sp.omega
+        d.tol = sp.tol
+        d.max_iters = sp.max_iters
+        d.check_every = sp.check_every
+    res = (_Result * len(specs))()
+    st = ctx.lib.sor_batch_solve_f64(ctx.handle, descs, len(specs),
+                                     _stream_handle(specs[0].u), res)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    return [_result(r.status, r) for r in res]
 
 
 def _solve_plain(fn, dtype, u, boundary, rhs, omega, tol, max_iters,

@@ -23,43 +23,11 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sor.h"
-#include "sor_internal.h"
+#include "sor_host.h"
 
 using namespace sor;
 
-namespace {
-
-struct DevBuf {
-  void *p = nullptr;
-  size_t bytes = 0;
-};
-
-enum BufRole {
-  kGridA64, kGridB64, kF64Buf,     // plain FP64 solve; U64 of the mixed solve
-  kGridA32, kGridB32, kF32Buf,     // plain FP32 solve; inner grids of mixed
-  kLoRhs,                          // inner right-hand side of the mixed solve
-  kPartials, kStats, kCtlBuf,
-  kNumRoles
-};
-
-}  // namespace
-
-struct sor_ctx {
-  int device = 0;
-  std::string err;
-  int kernel = SOR_KERNEL_BLOCKED;
-  sor_tiling tiling[3] = {{4, 192}, {4, 96}, {4, 96}};  // by Prec
-  DevBuf bufs[kNumRoles];
-  Ctl *host_ctl = nullptr;                             // pinned mirror
-  double *host_stats = nullptr;                        // pinned [4]
-  bool prof = false;                                   // time sweep launches
-  std::vector<hipEvent_t> events;                      // start/stop pairs
-  double prof_ms = 0.0;
-  int64_t prof_launches = 0;
-};
-
-namespace {
+namespace sor {
 
 sor_status fail(sor_ctx *c, sor_status st, const char *fmt, ...) {
   char buf[512];
@@ -70,13 +38,6 @@ sor_status fail(sor_ctx *c, sor_status st, const char *fmt, ...) {
   if (c) c->err = buf;
   return st;
 }
-
-#define HIP_TRY(ctx, expr)                                                   \
-  do {                                                                       \
-    hipError_t e_ = (expr);                                                  \
-    if (e_ != hipSuccess)                                                    \
-      return fail((ctx), SOR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
 
 sor_status ensure(sor_ctx *c, BufRole role, size_t bytes) {
   DevBuf &b = c->bufs[role];
@@ -99,11 +60,6 @@ sor_status ensure(sor_ctx *c, BufRole role, size_t bytes) {
   return SOR_OK;
 }
 
-template <typename T>
-T *origin(sor_ctx *c, BufRole role, const Layout &L) {
-  return (T *)c->bufs[role].p + L.origin_off();
-}
-
 bool is_device_ptr(sor_ctx *c, const void *p) {
   if (!p) return false;
   hipPointerAttribute_t a;
@@ -120,7 +76,7 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
                         const void *rhs, int32_t n, double omega) {
   if (!c) return SOR_EINVAL;
   c->err.clear();
-  if (n < 1 || n > (1 << 20)) return fail(c, SOR_EINVAL, "n = %d out of range", n);
+  if (n < 1 || n > kMaxN) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN);
   if (!(omega > 0.0 && omega < 2.0))
     return fail(c, SOR_EINVAL, "omega = %g outside (0, 2)", omega);
   if (!is_device_ptr(c, u)) return fail(c, SOR_EINVAL, "u is not a device pointer on device %d", c->device);
@@ -131,6 +87,15 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
 }
 
 int prec_index(int bits) { return bits == 64 ? kF64 : bits == 32 ? kF32 : bits == 16 ? kF16 : -1; }
+
+}  // namespace sor
+
+namespace {
+
+template <typename T>
+T *origin(sor_ctx *c, BufRole role, const Layout &L) {
+  return (T *)c->bufs[role].p + L.origin_off();
+}
 
 GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *in,
                    void *out, const void *F, double omega) {
@@ -193,7 +158,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       void **result_grid) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
-  const sor_tiling tl = c->tiling[prec];
+  const sor_tiling tl = tuned_tiling(c, prec, L.n);
   const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega);
@@ -374,6 +339,7 @@ void sor_ctx_destroy(sor_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  batch_state_free(c);
   for (DevBuf &b : c->bufs)
     if (b.p) (void)hipFree(b.p);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);
@@ -422,6 +388,7 @@ sor_status sor_ctx_set_tiling(sor_ctx *c, int32_t bits, const sor_tiling *t) {
     nt.seg_rows = t->seg_rows;
   }
   c->tiling[p] = nt;
+  clear_tuning(c, p);
   return SOR_OK;
 }
 

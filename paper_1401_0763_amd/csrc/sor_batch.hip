@@ -1,0 +1,306 @@
+// Batched red-black SOR: many independent grids of different sizes, each
+// with its own omega, tolerance and iteration limit, advanced by one
+// persistent kernel (one wavefront per work item).
+//
+// Every grid follows Algorithm 1 of Mittal 2014 exactly as a single solve
+// does (same blocked passes, same per-iteration maxima, same stopping rule
+// and re-run of a truncated pass), so each grid's result is bit-identical to
+// solving it alone, whatever else is in the batch.
+#include "sor_kernels.h"
+
+namespace sor {
+
+// Depths a batched pass may have; a re-run or a final partial pass is split
+// greedily into these.
+__device__ __forceinline__ int batch_depth(long long left, int T) {
+  if (T >= 4 && left >= 4) return 4;
+  if (T >= 2 && left >= 2) return 2;
+  return 1;
+}
+
+__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish the tiles 0..ntiles-1 of grid g (whole wave).
+__device__ void bq_publish(BQueue *q, BItem *ring, int g, int ntiles) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0)
+    base = __hip_atomic_fetch_add(&q->tail, (unsigned long long)ntiles,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, 0, 64);
+  const unsigned long long gen = q->gen, mask = q->mask;
+  for (int i = lane; i < ntiles; i += 64) {
+    const unsigned long long idx = base + (unsigned long long)i;
+    BItem *it = &ring[idx & mask];
+    __hip_atomic_store(&it->payload, ((unsigned long long)g << 32) | (unsigned)i,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&it->tag, bq_tag(gen, idx), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Take the next item.  Returns false when no grid has work left (or a wait
+// exceeded the deadline, which raises q->error).  Every lane waits.
+__device__ bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long idx = 0;
+  if (lane == 0)
+    idx = __hip_atomic_fetch_add(&q->head, 1ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  idx = __shfl(idx, 0, 64);
+  BItem *it = &ring[idx & q->mask];
+  const unsigned long long want = bq_tag(q->gen, idx);
+  const long long t0 = wall_clock64();
+  for (;;) {
+    if (ld_acq(&it->tag) == want) break;
+    if (__hip_atomic_load(&q->remaining, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= 0)
+      return false;
+    if (__hip_atomic_load(&q->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
+    if (wall_clock64() - t0 > q->deadline_ticks) {
+      if (lane == 0)
+        __hip_atomic_fetch_or(&q->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  const unsigned long long p = __hip_atomic_load(&it->payload, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  g = (int)(p >> 32);
+  tile = (int)(p & 0xffffffffu);
+  return true;
+}
+
+// Grid g finished the pass whose tiles were queued: evaluate Algorithm 1's
+// check for its iterations, then queue the next pass or retire the grid.
+// Called by the whole wave that completed the pass's last tile.
+template <int P>
+__device__ void batch_grid_finish(BGrid *G, int g, BQueue *q, BItem *ring) {
+  const int lane = threadIdx.x & 63;
+  const int T = G->pass_T;
+  double it_max[kTMax];
+#pragma unroll
+  for (int t = 0; t < kTMax; ++t) {
+    unsigned long long b = 0;
+    if (lane < kBSlots && t < T) {
+      b = __hip_atomic_load(&G->slots[lane][t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&G->slots[lane][t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    it_max[t] = wave_max(__longlong_as_double((long long)b));
+  }
+  int next_T = 0;   // depth of the next pass, 0: retire the grid
+  int nt = 0;       // its tiles
+  if (lane == 0) {
+    const unsigned nonf = __hip_atomic_load(&G->nonfinite, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    G->passes += 1;
+    G->pass_budget -= 1;
+    if (G->mode == 0) {
+      const long long it0 = G->it_base;
+      long long stop_at = 0;
+      for (int t = 0; t < T; ++t) {
+        const long long it = it0 + t + 1;
+        if (stop_at == 0 && (it % G->check_every == 0 || it == G->max_iters)) {
+          G->last_max = it_max[t];
+          if (it_max[t] < G->tol) {
+            stop_at = it;
+            G->stop_iter = it;
+            G->stop_max = it_max[t];
+          }
+        }
+      }
+      if (nonf) {
+        G->status = 3;
+        G->cur ^= 1;
+        G->it_base = it0 + T;
+        G->stop_iter = it0 + T;
+      } else if (stop_at == it0 + T) {
+        G->cur ^= 1;
+        G->it_base = stop_at;
+        G->status = 1;
+      } else if (stop_at != 0) {
+        // Met inside the pass: redo its first (stop_at - it0) iterations from
+        // the pass input, which is still in place (grid `cur`).
+        G->mode = 1;
+        G->rerun_left = stop_at - it0;
+        G->it_base = it0;
+        next_T = batch_depth(G->rerun_left, G->T);
+      } else {
+        G->cur ^= 1;
+        G->it_base = it0 + T;
+        if (G->it_base >= G->max_iters) {
+          G->status = 2;
+          G->stop_iter = G->max_iters;
+          G->stop_max = G->last_max;
+        } else if (G->pass_budget <= 0) {
+          G->status = 4;
+        } else {
+          next_T = batch_depth(G->max_iters - G->it_base, G->T);
+        }
+      }
+    } else {
+      G->cur ^= 1;
+      G->it_base += T;
+      G->rerun_left -= T;
+      if (G->rerun_left <= 0) {
+        G->status = 1;
+        G->mode = 0;
+      } else {
+        next_T = batch_depth(G->rerun_left, G->T);
+      }
+    }
+    if (next_T) {
+      nt = blocked_ntiles(P, G->n, next_T, G->seg_rows);
+      G->pass_T = next_T;
+      G->ntiles = nt;
+    }
+    __hip_atomic_store(&G->tiles_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  next_T = __shfl(next_T, 0, 64);
+  nt = __shfl(nt, 0, 64);
+  if (next_T) {
+    bq_publish(q, ring, g, nt);
+  } else if (lane == 0) {
+    __hip_atomic_fetch_add(&q->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <int P, int T, bool POIS>
+__device__ __forceinline__ void batch_tile(BGrid *G, int tile, double (&mx)[kTMax],
+                                           bool &bad) {
+  using ct = typename PT<P>::ct;
+  constexpr int V = PT<P>::V;
+  constexpr int S = 2 * T;
+  constexpr int A = ((S + V - 1) / V) * V;
+  constexpr int CW = kLanes * V - 2 * A;
+  GridView v;
+  v.in = G->cur ? G->B : G->A;
+  v.out = G->cur ? G->A : G->B;
+  v.F = G->F;
+  v.pitch = G->pitch;
+  v.n = G->n;
+  v.seg_rows = G->seg_rows;
+  v.nstrips = (v.n + 1 + CW - 1) / CW;
+  v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
+  v.omega = G->omega;
+  const int strip = tile % v.nstrips, seg = tile / v.nstrips;
+  const int j0 = strip * CW - A;
+  const int a = seg * v.seg_rows - S;
+  const int b = min(a + S + v.seg_rows, v.n + 1) + S;
+  const bool mask = (j0 < 1) || (j0 + kLanes * V - 1 > v.n) || (a < 1) || (b - 1 > v.n);
+  ct m[T];
+  if (mask)
+    blocked_tile<P, T, POIS, true>(v, tile, m, bad);
+  else
+    blocked_tile<P, T, POIS, false>(v, tile, m, bad);
+#pragma unroll
+  for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
+}
+
+// Persistent batched sweep: each wavefront takes items until no grid has work
+// left.  Items of a grid's pass run in any order on any wavefront; the last
+// one to finish closes the pass.
+template <int P>
+__global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BItem *ring) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int g, tile;
+    if (!bq_take(q, ring, g, tile)) return;
+    BGrid *G = &grids[g];
+    const int T = G->pass_T;
+    const bool pois = G->F != nullptr;
+    double mx[kTMax];
+#pragma unroll
+    for (int t = 0; t < kTMax; ++t) mx[t] = 0.0;
+    bool bad = false;
+    if (pois) {
+      if (T == 4) batch_tile<P, 4, true>(G, tile, mx, bad);
+      else if (T == 2) batch_tile<P, 2, true>(G, tile, mx, bad);
+      else batch_tile<P, 1, true>(G, tile, mx, bad);
+    } else {
+      if (T == 4) batch_tile<P, 4, false>(G, tile, mx, bad);
+      else if (T == 2) batch_tile<P, 2, false>(G, tile, mx, bad);
+      else batch_tile<P, 1, false>(G, tile, mx, bad);
+    }
+    const bool anybad = __ballot(bad) != 0;
+    unsigned prev = 0;
+    if (lane == 0) {
+      if (G->mode == 0) {
+        const int slot = tile % kBSlots;
+        for (int t = 0; t < T; ++t)
+          __hip_atomic_fetch_max(&G->slots[slot][t],
+                                 (unsigned long long)__double_as_longlong(mx[t]),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (anybad)
+          __hip_atomic_fetch_or(&G->nonfinite, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      prev = __hip_atomic_fetch_add(&G->tiles_done, 1u, __ATOMIC_ACQ_REL,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = __shfl(prev, 0, 64);
+    if (prev == (unsigned)G->ntiles - 1) batch_grid_finish<P>(G, g, q, ring);
+  }
+}
+
+// Pack every grid's caller arrays into its working grid A (and the ring into
+// B), and F = h*h*f.  Block (x, y): rows x*... of grid y.
+__global__ void batch_pack_kernel(const BGrid *grids, int count) {
+  const BGrid &G = grids[blockIdx.y];
+  const int n = G.n;
+  const int r = blockIdx.x;                 // row 0 .. n+1
+  if (r > n + 1) return;
+  double *A = (double *)G.A, *B = (double *)G.B;
+  double *F = (double *)G.F;
+  const double h = 1.0 / (double)(n + 1);
+  const double h2 = h * h;
+  for (int c = threadIdx.x; c <= n + 1; c += blockDim.x) {
+    const bool in_r = r >= 1 && r <= n, in_c = c >= 1 && c <= n;
+    double val = 0.0;
+    if (in_r && in_c) val = G.user_u[(int64_t)(r - 1) * n + (c - 1)];
+    else if (r == 0 && in_c) val = G.user_bdy[c - 1];
+    else if (r == n + 1 && in_c) val = G.user_bdy[n + c - 1];
+    else if (c == 0 && in_r) val = G.user_bdy[2 * n + r - 1];
+    else if (c == n + 1 && in_r) val = G.user_bdy[3 * n + r - 1];
+    const int64_t o = (int64_t)r * G.pitch + c;
+    A[o] = val;
+    if (!(in_r && in_c)) B[o] = val;
+    if (F) F[o] = (in_r && in_c) ? h2 * G.user_f[(int64_t)(r - 1) * n + (c - 1)] : 0.0;
+  }
+}
+
+__global__ void batch_unpack_kernel(const BGrid *grids, int count) {
+  const BGrid &G = grids[blockIdx.y];
+  const int n = G.n;
+  const int r = blockIdx.x + 1;
+  if (r > n) return;
+  const double *S = (const double *)(G.cur ? G.B : G.A);
+  for (int c = threadIdx.x; c < n; c += blockDim.x)
+    G.user_u[(int64_t)(r - 1) * n + c] = S[(int64_t)r * G.pitch + c + 1];
+}
+
+hipError_t launch_batch_pack(const BGrid *grids, int count, int max_n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_pack_kernel, dim3(max_n + 2, count), dim3(256), 0, s, grids, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_unpack_kernel, dim3(max_n, count), dim3(256), 0, s, grids, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, int waves, hipStream_t s) {
+  hipLaunchKernelGGL(batch_kernel<kF64>, dim3(waves), dim3(64), 0, s, grids, q, ring);
+  return hipGetLastError();
+}
+
+int batch_waves_per_cu_f64() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<kF64>, 64, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 8;
+  }
+  return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace sor

@@ -1,0 +1,374 @@
+// Host side of batched solves and of the tiling autotuner (C ABI in
+// include/sor.h).
+//
+// A batch is laid out in one device arena (each grid's padded A and B grids
+// and its h*h*f grid), described by an array of BGrid records, and advanced by
+// one persistent kernel fed from a device ring buffer of (grid, tile) items.
+// The upload / pack / persistent kernel / unpack / download sequence is
+// captured once as a HIP graph and replayed while the batch shapes repeat
+// (the graph reads the descriptors from pinned host staging buffers, so new
+// caller pointers and parameters take effect on every replay).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "sor_host.h"
+
+namespace sor {
+
+struct BatchState {
+  hipStream_t stream = nullptr;          // internal stream (graph capture)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  BGrid *h_grids = nullptr;              // pinned staging
+  size_t h_grids_cap = 0;
+  BQueue *h_queue = nullptr;
+  BItem *h_items = nullptr;
+  size_t h_items_cap = 0;
+  unsigned long long gen = 0;
+  long long wall_khz = 0;
+  hipGraphExec_t exec = nullptr;
+  std::vector<long long> sig;            // shapes the graph was recorded for
+  // size class -> tiling, per precision (autotuner results)
+  std::map<int, sor_tiling> tune[3];
+};
+
+void batch_state_free(sor_ctx *c) {
+  BatchState *b = c->batch;
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->h_grids) (void)hipHostFree(b->h_grids);
+  if (b->h_queue) (void)hipHostFree(b->h_queue);
+  if (b->h_items) (void)hipHostFree(b->h_items);
+  delete b;
+  c->batch = nullptr;
+}
+
+// Size class of a grid side: nearest half power of two (so 64, 90, 128, ...).
+int size_class(int n) { return (int)std::lround(2.0 * std::log2((double)std::max(n, 1))); }
+
+// Tiling for a grid of side n at precision prec: the autotuned entry of its
+// class if there is one, else the context's tiling for large grids and a
+// shallower, shorter tile for small ones (which have few tiles per pass).
+sor_tiling tiling_for(sor_ctx *c, int prec, int n) {
+  if (c->batch) {
+    auto &m = c->batch->tune[prec];
+    auto it = m.find(size_class(n));
+    if (it != m.end()) return it->second;
+  }
+  sor_tiling t = c->tiling[prec];
+  if (n < 512) {
+    t.iters_per_pass = std::min(t.iters_per_pass, 4);
+    t.seg_rows = std::min(t.seg_rows, 64);
+  }
+  return t;
+}
+
+sor_tiling tuned_tiling(sor_ctx *c, int prec, int n) {
+  if (c->batch) {
+    auto &m = c->batch->tune[prec];
+    auto it = m.find(size_class(n));
+    if (it != m.end()) return it->second;
+  }
+  return c->tiling[prec];
+}
+
+void clear_tuning(sor_ctx *c, int prec) {
+  if (c->batch) c->batch->tune[prec].clear();
+}
+
+namespace {
+
+sor_status batch_state(sor_ctx *c, BatchState **out) {
+  if (!c->batch) {
+    BatchState *b = new (std::nothrow) BatchState;
+    if (!b) return fail(c, SOR_ENOMEM, "out of host memory");
+    c->batch = b;
+    HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    HIP_TRY(c, hipHostMalloc((void **)&b->h_queue, sizeof(BQueue), hipHostMallocDefault));
+    int khz = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
+    b->wall_khz = khz > 0 ? khz : 100000;
+  }
+  *out = c->batch;
+  return SOR_OK;
+}
+
+template <typename T>
+sor_status host_grow(sor_ctx *c, T **p, size_t *cap, size_t need) {
+  if (*cap >= need) return SOR_OK;
+  if (*p) (void)hipHostFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t n = std::max(need, *cap * 2);
+  HIP_TRY(c, hipHostMalloc((void **)p, n * sizeof(T), hipHostMallocDefault));
+  *cap = n;
+  return SOR_OK;
+}
+
+// Batch depths are 1, 2 or 4 iterations per pass.
+int batch_T(int T) { return T >= 4 ? 4 : T >= 2 ? 2 : 1; }
+long long batch_depth_host(long long left, int T) {
+  if (T >= 4 && left >= 4) return 4;
+  if (T >= 2 && left >= 2) return 2;
+  return 1;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+}  // namespace sor
+
+using namespace sor;
+
+extern "C" {
+
+sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t count,
+                               void *stream, sor_result *results) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (!grids || !results || count < 1) return fail(c, SOR_EINVAL, "need grids, results and count >= 1");
+  HIP_TRY(c, hipSetDevice(c->device));
+  for (int g = 0; g < count; ++g) {
+    const sor_grid_desc &d = grids[g];
+    sor_status st = check_common(c, d.u, d.boundary, d.rhs, d.n, d.omega);
+    if (st != SOR_OK) return fail(c, st, "grid %d: %s", g, c->err.c_str());
+    if (!(d.tol >= 0.0) || d.max_iters < 1 || d.check_every < 1)
+      return fail(c, SOR_EINVAL, "grid %d: tol, max_iters or check_every invalid", g);
+  }
+  BatchState *bs = nullptr;
+  sor_status st = batch_state(c, &bs);
+  if (st != SOR_OK) return st;
+
+  // Arena layout, tilings and work estimates.
+  std::vector<Layout> lay(count);
+  std::vector<size_t> offA(count), offB(count), offF(count);
+  std::vector<sor_tiling> til(count);
+  size_t arena = 0;
+  long long total_items = 0, max_items = 0;
+  int max_n = 0;
+  for (int g = 0; g < count; ++g) {
+    const int n = grids[g].n;
+    lay[g] = make_layout(n, kF64);
+    const size_t bytes = align_up((size_t)lay[g].elems() * sizeof(double), 256);
+    offA[g] = arena; arena += bytes;
+    offB[g] = arena; arena += bytes;
+    if (grids[g].rhs) { offF[g] = arena; arena += bytes; }
+    til[g] = tiling_for(c, kF64, n);
+    til[g].iters_per_pass = batch_T(til[g].iters_per_pass);
+    const int T0 = (int)batch_depth_host(grids[g].max_iters, til[g].iters_per_pass);
+    total_items += blocked_ntiles(kF64, n, T0, til[g].seg_rows);
+    long long most = 0;
+    for (int t : {1, 2, 4})
+      most = std::max<long long>(most, blocked_ntiles(kF64, n, t, til[g].seg_rows));
+    max_items += most;
+    max_n = std::max(max_n, n);
+  }
+  // Ring capacity: every grid has at most one pass queued, plus one slot per
+  // waiting wavefront; doubled and rounded to a power of two.
+  int cus = 0;
+  HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+  const int waves = std::max(1, cus) * batch_waves_per_cu_f64();
+  unsigned long long cap = 1024;
+  while (cap < 2ull * (unsigned long long)(max_items + waves) + 1024) cap <<= 1;
+
+  if ((st = ensure(c, kBatchArena, arena)) ||
+      (st = ensure(c, kBatchGrids, sizeof(BGrid) * (size_t)count)) ||
+      (st = ensure(c, kBatchQueue, sizeof(BQueue))) ||
+      (st = ensure(c, kBatchRing, sizeof(BItem) * cap)))
+    return st;
+  if ((st = host_grow(c, &bs->h_grids, &bs->h_grids_cap, (size_t)count)) ||
+      (st = host_grow(c, &bs->h_items, &bs->h_items_cap, (size_t)total_items)))
+    return st;
+
+  char *base = (char *)c->bufs[kBatchArena].p;
+  for (int g = 0; g < count; ++g) {
+    const sor_grid_desc &d = grids[g];
+    BGrid &G = bs->h_grids[g];
+    std::memset(&G, 0, sizeof(BGrid));
+    const size_t org = (size_t)lay[g].origin_off() * sizeof(double);
+    G.A = base + offA[g] + org;
+    G.B = base + offB[g] + org;
+    G.F = d.rhs ? base + offF[g] + org : nullptr;
+    G.user_u = d.u;
+    G.user_bdy = d.boundary;
+    G.user_f = d.rhs;
+    G.pitch = lay[g].pitch;
+    G.n = d.n;
+    G.T = til[g].iters_per_pass;
+    G.seg_rows = til[g].seg_rows;
+    G.omega = d.omega;
+    G.tol = d.tol;
+    G.max_iters = d.max_iters;
+    G.check_every = d.check_every;
+    G.pass_budget = LLONG_MAX;
+    G.pass_T = (int)batch_depth_host(d.max_iters, G.T);
+    G.ntiles = blocked_ntiles(kF64, d.n, G.pass_T, G.seg_rows);
+    G.last_max = NAN;
+  }
+  // Initial queue: pass 0 of every grid, largest expected work first (work
+  // grows like n^3 at the optimal omega) so the longest chains start first.
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return grids[x].n > grids[y].n; });
+  const unsigned long long gen = ++bs->gen & 0xffffffull;
+  unsigned long long idx = 0;
+  for (int g : order)
+    for (int t = 0; t < bs->h_grids[g].ntiles; ++t, ++idx) {
+      bs->h_items[idx].tag = bq_tag(gen, idx);
+      bs->h_items[idx].payload = ((unsigned long long)g << 32) | (unsigned)t;
+    }
+  BQueue &Q = *bs->h_queue;
+  std::memset(&Q, 0, sizeof(BQueue));
+  Q.head = 0;
+  Q.tail = idx;
+  Q.gen = gen;
+  Q.mask = cap - 1;
+  Q.remaining = count;
+  Q.error = 0;
+  Q.deadline_ticks = bs->wall_khz * 1000ll * 20;   // 20 s without progress
+
+  BGrid *dG = (BGrid *)c->bufs[kBatchGrids].p;
+  BQueue *dQ = (BQueue *)c->bufs[kBatchQueue].p;
+  BItem *dR = (BItem *)c->bufs[kBatchRing].p;
+  const std::vector<long long> sig = {
+      count, (long long)total_items, max_n, waves, (long long)cap,
+      (long long)(uintptr_t)base, (long long)(uintptr_t)dG, (long long)(uintptr_t)dQ,
+      (long long)(uintptr_t)dR, (long long)(uintptr_t)bs->h_grids,
+      (long long)(uintptr_t)bs->h_queue, (long long)(uintptr_t)bs->h_items};
+  bool record = !(bs->exec && bs->sig == sig);
+  hipStream_t s = bs->stream;
+  HIP_TRY(c, hipEventRecord(bs->ev_in, (hipStream_t)stream));
+  HIP_TRY(c, hipStreamWaitEvent(s, bs->ev_in, 0));
+  if (record) {
+    if (bs->exec) { (void)hipGraphExecDestroy(bs->exec); bs->exec = nullptr; }
+    hipGraph_t graph = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    auto step = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    step(hipMemcpyAsync(dG, bs->h_grids, sizeof(BGrid) * count, hipMemcpyHostToDevice, s));
+    step(hipMemcpyAsync(dQ, bs->h_queue, sizeof(BQueue), hipMemcpyHostToDevice, s));
+    step(hipMemcpyAsync(dR, bs->h_items, sizeof(BItem) * total_items, hipMemcpyHostToDevice, s));
+    step(launch_batch_pack(dG, count, max_n, s));
+    step(launch_batch_f64(dG, dQ, dR, waves, s));
+    step(launch_batch_unpack(dG, count, max_n, s));
+    step(hipMemcpyAsync(bs->h_grids, dG, sizeof(BGrid) * count, hipMemcpyDeviceToHost, s));
+    step(hipMemcpyAsync(bs->h_queue, dQ, sizeof(BQueue), hipMemcpyDeviceToHost, s));
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return fail(c, SOR_EDEVICE, "graph capture failed: %s",
+                  hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&bs->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      bs->exec = nullptr;
+      return fail(c, SOR_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    bs->sig = sig;
+  }
+  HIP_TRY(c, hipGraphLaunch(bs->exec, s));
+  HIP_TRY(c, hipEventRecord(bs->ev_out, s));
+  HIP_TRY(c, hipStreamWaitEvent((hipStream_t)stream, bs->ev_out, 0));
+  HIP_TRY(c, hipStreamSynchronize(s));
+
+  if (bs->h_queue->error) return fail(c, SOR_ETIMEOUT, "a queue wait exceeded its bound");
+  sor_status overall = SOR_OK;
+  for (int g = 0; g < count; ++g) {
+    const BGrid &G = bs->h_grids[g];
+    sor_result &r = results[g];
+    r = sor_result{};
+    r.rel_residual = NAN;
+    r.passes = G.passes;
+    r.iterations = G.status == 2 ? G.max_iters : G.stop_iter;
+    r.final_max_delta = G.stop_max;
+    r.converged = G.status == 1;
+    switch (G.status) {
+      case 1: r.status = SOR_OK; break;
+      case 2: r.status = SOR_NOT_CONVERGED; break;
+      case 3: r.status = SOR_ENONFINITE; break;
+      default: r.status = SOR_EDEVICE; break;
+    }
+    if (r.status == SOR_ENONFINITE) overall = SOR_ENONFINITE;
+    else if (r.status == SOR_EDEVICE && overall >= 0) overall = SOR_EDEVICE;
+    else if (r.status == SOR_NOT_CONVERGED && overall == SOR_OK) overall = SOR_NOT_CONVERGED;
+  }
+  if (overall == SOR_EDEVICE) return fail(c, SOR_EDEVICE, "a grid did not finish");
+  return overall;
+}
+
+sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  const int prec = prec_index(bits);
+  if (prec != kF64 && prec != kF32) return fail(c, SOR_EINVAL, "bits must be 64 or 32");
+  if (n < 1 || n > kMaxN) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN);
+  HIP_TRY(c, hipSetDevice(c->device));
+  BatchState *bs = nullptr;
+  sor_status st = batch_state(c, &bs);
+  if (st != SOR_OK) return st;
+  const Layout L = make_layout(n, prec);
+  const size_t bytes = (size_t)L.elems() * (size_t)prec_bytes(prec);
+  const BufRole ra = prec == kF64 ? kGridA64 : kGridA32;
+  const BufRole rb = prec == kF64 ? kGridB64 : kGridB32;
+  if ((st = ensure(c, ra, bytes)) || (st = ensure(c, rb, bytes))) return st;
+  char *A = (char *)c->bufs[ra].p + L.origin_off() * prec_bytes(prec);
+  char *B = (char *)c->bufs[rb].p + L.origin_off() * prec_bytes(prec);
+  hipStream_t s = bs->stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  const Sched sc{1, 1, 0.0};
+  sor_tiling bt{c->tiling[prec].iters_per_pass, c->tiling[prec].seg_rows};
+  double best_t = INFINITY;
+  hipError_t e = hipSuccess;
+  for (int T : {1, 2, 3, 4, 6}) {
+    for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384}) {
+      if (seg > 2 * (n + 1) && seg != 16) continue;
+      GridView v;
+      v.in = A; v.out = B; v.F = nullptr; v.pitch = L.pitch; v.n = n;
+      v.seg_rows = seg; v.omega = 1.5;
+      const BlockGeom gm = block_geom(prec, T);
+      v.nstrips = (n + 1 + gm.CW - 1) / gm.CW;
+      v.nseg = (n + 1 + seg - 1) / seg;
+      const int reps = 3;
+      if (e == hipSuccess) e = launch_blocked_pass(prec, T, v, nullptr, sc, s);   // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, s);
+      for (int k = 0; k < reps && e == hipSuccess; ++k) {
+        std::swap(v.in, *(const void **)&v.out);
+        e = launch_blocked_pass(prec, T, v, nullptr, sc, s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      const double per_iter = ms / (reps * T);
+      if (per_iter < best_t) {
+        best_t = per_iter;
+        bt.iters_per_pass = T;
+        bt.seg_rows = seg;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(c, SOR_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  bs->tune[prec][size_class(n)] = bt;
+  if (best) *best = bt;
+  return SOR_OK;
+}
+
+}  // extern "C"

@@ -23,14 +23,16 @@ constexpr int kTMax = 8;          // most iterations one blocked pass applies
 constexpr int kSlots = 64;        // partial-maximum slots per pass
 constexpr int kHistCap = 1024;    // per-iteration maxima kept per solve chunk
 constexpr int kLanes = 64;        // wavefront width on CDNA
+constexpr int kMaxN = 65536;      // largest grid side (32-bit buffer offsets)
+constexpr int kMaxSegRows = 1024; // largest rows per tile
 
 // Storage precisions.
 enum Prec : int { kF64 = 0, kF32 = 1, kF16 = 2 };
 
-inline int prec_bytes(int prec) { return prec == kF64 ? 8 : prec == kF32 ? 4 : 2; }
+__host__ __device__ inline int prec_bytes(int prec) { return prec == kF64 ? 8 : prec == kF32 ? 4 : 2; }
 // Cells held per lane by the blocked kernel (one 16-byte access for FP64 and
 // FP32, one 8-byte access for FP16 storage).
-inline int prec_cells(int prec) { return prec == kF64 ? 2 : 4; }
+__host__ __device__ inline int prec_cells(int prec) { return prec == kF64 ? 2 : 4; }
 
 struct Layout {
   int32_t n = 0;
@@ -79,6 +81,92 @@ struct GridView {
   int32_t seg_rows;     // output rows per segment (even)
   double omega;
 };
+
+// ---------------------------------------------------------------------------
+// Batched solves: many grids advanced by one persistent kernel.
+//
+// Work items are (grid, tile) pairs of one pass of one grid.  They live in a
+// ring buffer; the wave that finishes the last tile of a grid's pass
+// evaluates that grid's stopping rule and publishes the tiles of its next
+// pass, so an item is only ever published after everything it depends on has
+// completed.  Each slot carries a tag (launch generation, index) that the
+// consumer waits for.
+// ---------------------------------------------------------------------------
+constexpr int kBSlots = 8;          // partial-maximum slots per grid
+
+struct alignas(128) BGrid {
+  // Set by the host.
+  void *A;                 // origin of working grid A (FP64 or storage type)
+  void *B;                 // origin of working grid B
+  const void *F;           // origin of h*h*f, or nullptr
+  double *user_u;          // caller's n*n interior (in: guess, out: result)
+  const double *user_bdy;  // caller's 4n boundary
+  const double *user_f;    // caller's n*n source, or nullptr
+  int64_t pitch;
+  int32_t n;
+  int32_t T;               // iterations per full pass
+  int32_t seg_rows;
+  int32_t pad0;
+  double omega;
+  double tol;
+  int64_t max_iters;
+  int64_t check_every;
+  int64_t pass_budget;     // passes this launch may run before pausing
+  // Device state (the host initialises it, the kernel advances it).
+  int32_t cur;             // 0: the iterate is in A, 1: in B
+  int32_t status;          // 0 running, 1 converged, 2 iteration limit,
+                           // 3 non-finite, 4 paused (budget spent)
+  int32_t mode;            // 0 normal passes, 1 re-running a truncated pass
+  int32_t pass_T;          // depth of the pass whose tiles are queued
+  int32_t ntiles;          // tiles of that pass
+  uint32_t tiles_done;
+  uint32_t nonfinite;
+  int32_t pad1;
+  int64_t it_base;         // iterations completed
+  int64_t rerun_left;      // iterations still to redo in re-run mode
+  int64_t stop_iter;
+  int64_t passes;          // passes completed (all launches)
+  double stop_max;
+  double last_max;         // change at the last checked iteration
+  unsigned long long slots[kBSlots][kTMax];
+};
+
+struct alignas(128) BQueue {
+  unsigned long long head;   // next index to take
+  unsigned long long tail;   // next index to publish
+  unsigned long long gen;    // generation of this launch (tag high bits)
+  unsigned long long mask;   // ring capacity - 1 (power of two)
+  int remaining;             // grids that still have queued work
+  int error;                 // 1: a wait timed out
+  long long deadline_ticks;  // wait limit in wall-clock ticks
+};
+
+struct BItem {
+  unsigned long long tag;      // (gen << 40) | (index + 1) once published
+  unsigned long long payload;  // (grid << 32) | tile
+};
+
+__host__ __device__ inline unsigned long long bq_tag(unsigned long long gen, unsigned long long idx) {
+  return (gen << 40) | (idx + 1);
+}
+
+// Tiles of one blocked pass of depth T over an n-grid.
+__host__ __device__ inline int blocked_ntiles(int prec, int n, int T, int seg_rows) {
+  const int V = prec_cells(prec);
+  const int S = 2 * T;
+  const int A = ((S + V - 1) / V) * V;
+  const int CW = kLanes * V - 2 * A;
+  return ((n + 1 + CW - 1) / CW) * ((n + 1 + seg_rows - 1) / seg_rows);
+}
+
+hipError_t launch_batch_pack(const BGrid *grids, int count, int max_n,
+                             hipStream_t s);
+hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n,
+                               hipStream_t s);
+// Persistent batched sweep (FP64 storage).  waves: persistent wavefronts.
+hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, int waves,
+                            hipStream_t s);
+int batch_waves_per_cu_f64();
 
 // Geometry of the blocked kernel for a precision and iterations-per-pass T.
 struct BlockGeom {
