@@ -237,6 +237,93 @@ sor_status sor_batch_solve_f64(sor_ctx *ctx, const sor_grid_desc *grids,
  */
 sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best);
 
+/*
+ * One grid of a mixed-precision batched solve or of a served request: the
+ * defect-correction method of sor_solve_mixed, with its parameters per grid.
+ */
+typedef struct sor_mixed_desc {
+    double *u;                /* device n*n: in initial guess, out result   */
+    const double *boundary;   /* device 4n                                  */
+    const double *rhs;        /* device n*n, or NULL                        */
+    int32_t n;
+    int32_t reserved;
+    double omega;             /* inner SOR relaxation factor, in (0, 2)     */
+    double rel_tol;           /* stop when ||r||_2/||b||_2 <= rel_tol       */
+    double corr_tol;          /* or (if > 0) when the last correction's max
+                                 |e| is below corr_tol                      */
+    int64_t max_outer;        /* >= 0 corrections                           */
+    int64_t inner_iters;      /* > 0 inner iterations per correction
+                                 (<= 0 selects 2n)                          */
+} sor_mixed_desc;
+
+/*
+ * Batched mixed-precision solves: each grid gets exactly sor_solve_mixed's
+ * arithmetic (FP64 residual, inner right-hand side fl(r*2^p), inner_iters
+ * red-black SOR iterations in `inner_bits` storage (32 or 16) from zero,
+ * u += e*2^-p), bit for bit whatever else is in the batch; every grid's
+ * phases (residual, cast, inner passes, accumulate) are work items of one
+ * persistent kernel launch.  The residual-based test of sor_solve_mixed is
+ * extended by the optional corr_tol test, evaluated after the residual of
+ * the corrected iterate: converged when rel <= rel_tol, or when corr_tol > 0,
+ * at least one correction was applied and its max |e| < corr_tol.
+ * results[g].outer_steps, .rel_residual, .final_max_delta (last correction)
+ * and .iterations (inner iterations) describe each grid.
+ */
+sor_status sor_batch_solve_mixed(sor_ctx *ctx, const sor_mixed_desc *grids,
+                                 int32_t count, int32_t inner_bits, void *stream,
+                                 sor_result *results);
+
+/*
+ * Serving: a request loop on one GPU.  Requests (host arrays, copied at
+ * submission) wait in a FIFO until a slot and `hbm_budget` bytes of device
+ * memory are free; admitted requests keep their whole state on the device
+ * and are advanced together by time-sliced launches of the mixed-precision
+ * persistent kernel (each launch runs for about `slice_ms`, then newly
+ * arrived requests join and finished ones leave: continuous batching).
+ * A background host thread drives the loop; submit/poll are thread-safe.
+ */
+typedef struct sor_server sor_server;
+
+typedef struct sor_request {
+    const double *u0;         /* HOST n*n initial guess (NULL: zeros)       */
+    const double *boundary;   /* HOST 4n                                    */
+    const double *rhs;        /* HOST n*n or NULL                           */
+    int32_t n;
+    int32_t reserved;
+    double omega;             /* <= 0 selects 2/(1+sin(pi/(n+1)))           */
+    double rel_tol;
+    double corr_tol;
+    int64_t max_outer;
+    int64_t inner_iters;      /* <= 0 selects 2n                            */
+} sor_request;
+
+typedef struct sor_request_info {
+    sor_result result;
+    double submit_s;          /* server clock (seconds) at submission       */
+    double admit_s;           /* ... when it got a slot                     */
+    double done_s;            /* ... when its result reached the host       */
+} sor_request_info;
+
+sor_status sor_server_create(int device, int32_t inner_bits, size_t hbm_budget,
+                             int32_t max_slots, double slice_ms, sor_server **out);
+/* Copy a request in and queue it; *ticket identifies it.  SOR_EBUSY if the
+ * request alone exceeds the memory budget (it could never be admitted). */
+sor_status sor_server_submit(sor_server *srv, const sor_request *req, uint64_t *ticket);
+/* If the request has finished, fill *info and u_out (HOST n*n, may be NULL),
+ * release it and return its status (SOR_OK, SOR_NOT_CONVERGED, SOR_ENONFINITE);
+ * SOR_EBUSY while it is still queued or running; SOR_EINVAL for an unknown
+ * ticket.  wait_ms > 0 blocks up to that long for completion. */
+sor_status sor_server_poll(sor_server *srv, uint64_t ticket, double wait_ms,
+                           sor_request_info *info, double *u_out);
+/* Server clock now (seconds), and counters: launches, requests completed,
+ * requests waiting, requests resident. */
+double sor_server_clock(const sor_server *srv);
+sor_status sor_server_stats(sor_server *srv, int64_t *launches, int64_t *completed,
+                            int64_t *waiting, int64_t *resident);
+const char *sor_server_last_error(const sor_server *srv);
+/* Stop the loop (unfinished requests are dropped) and free everything. */
+void sor_server_destroy(sor_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -61,8 +61,8 @@ def _load():
     lib.oracle_residual_f64.argtypes = [ctypes.c_int, dp, dp, dp, dp, dp]
     lib.oracle_residual_f64.restype = ctypes.c_int
     lib.oracle_mixed.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
-                                 ctypes.c_double, ctypes.c_int64, ctypes.c_int,
-                                 ctypes.c_int64, i64p, dp, dp]
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                 ctypes.c_int, ctypes.c_int64, i64p, dp, dp, dp]
     lib.oracle_mixed.restype = ctypes.c_int
     lib.oracle_round_half.argtypes = [ctypes.c_float]
     lib.oracle_round_half.restype = ctypes.c_float
@@ -167,6 +167,7 @@ class MixedResult:
     outer_steps: int
     rel_residual: float
     relhist: np.ndarray
+    last_correction: float = float("nan")
 
     @property
     def converged(self) -> bool:
@@ -174,7 +175,7 @@ class MixedResult:
 
 
 def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
-          inner_iters=None) -> MixedResult:
+          inner_iters=None, corr_tol=0.0) -> MixedResult:
     """FP64 defect correction around reduced-precision red-black SOR."""
     lib = _load()
     n = int(np.asarray(bdy).size // 4)
@@ -184,14 +185,16 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
     outer = ctypes.c_int64(0)
     rel = ctypes.c_double(0.0)
     rh = np.zeros(max_outer + 1, dtype=np.float64)
+    corr = ctypes.c_double(0.0)
     st = lib.oracle_mixed(n, _ptr(u, ctypes.c_double), _ptr(b, ctypes.c_double),
                           _ptr(ff, ctypes.c_double), float(omega), float(rel_tol),
-                          int(max_outer), int(inner_bits), int(inner_iters),
-                          ctypes.byref(outer), ctypes.byref(rel),
-                          _ptr(rh, ctypes.c_double))
+                          float(corr_tol), int(max_outer), int(inner_bits),
+                          int(inner_iters), ctypes.byref(outer), ctypes.byref(rel),
+                          _ptr(rh, ctypes.c_double), ctypes.byref(corr))
     if st < 0:
         raise ValueError(f"oracle_mixed rejected its arguments (status {st})")
-    return MixedResult(u, st, outer.value, rel.value, rh[: outer.value + 1])
+    return MixedResult(u, st, outer.value, rel.value, rh[: outer.value + 1],
+                       corr.value)
 
 
 def round_half(x: float) -> float:

@@ -421,12 +421,16 @@ static int orc_scale_exp(double target, double rinf)
  * the correction is added as u = u + (double)e * 2^-p.
  * relhist (length max_outer + 1, may be NULL) receives rel before each
  * correction and the final rel.  *outer_out = number of corrections applied.
- * Returns ORC_OK when rel <= rel_tol was reached, else ORC_NOT_CONVERGED.
+ * corr_tol > 0 adds a second way to stop, tested after rel: at least one
+ * correction applied and the last one's max |e * 2^-p| below corr_tol (the
+ * change of u over one outer step).
+ * Returns ORC_OK when a stopping test passed, else ORC_NOT_CONVERGED.
  */
 int oracle_mixed(int n, double *u, const double *bdy, const double *f,
-                 double omega, double rel_tol, int64_t max_outer,
-                 int inner_bits, int64_t inner_iters, int64_t *outer_out,
-                 double *rel_out, double *relhist)
+                 double omega, double rel_tol, double corr_tol,
+                 int64_t max_outer, int inner_bits, int64_t inner_iters,
+                 int64_t *outer_out, double *rel_out, double *relhist,
+                 double *corr_out)
 {
     if (n < 1 || !u || !bdy || !(omega > 0.0 && omega < 2.0) ||
         !(rel_tol >= 0.0) || max_outer < 0 || inner_iters < 0 ||
@@ -450,13 +454,14 @@ int oracle_mixed(int n, double *u, const double *bdy, const double *f,
 
     int status = ORC_NOT_CONVERGED;
     int64_t outer = 0;
-    double rel = NAN;
+    double rel = NAN, last_corr = NAN;
     for (;;) {
         double st[3];
         orc_residual_core(n, U, F, r, st);
         rel = (st[1] > 0.0) ? sqrt(st[0]) / sqrt(st[1]) : sqrt(st[0]);
         if (relhist) relhist[outer] = rel;
         if (rel <= rel_tol || st[2] == 0.0) { status = ORC_OK; break; }
+        if (corr_tol > 0.0 && outer > 0 && last_corr < corr_tol) { status = ORC_OK; break; }
         if (outer == max_outer) break;
         int p = orc_scale_exp(target, st[2]);
         for (int i = 1; i <= n; ++i)
@@ -471,14 +476,19 @@ int oracle_mixed(int n, double *u, const double *bdy, const double *f,
             orc_half_sweep_f32(n, E, R, w, 1, half, &bad);
         }
         double inv = ldexp(1.0, -p);
+        last_corr = 0.0;
         for (int i = 1; i <= n; ++i)
-            for (int j = 1; j <= n; ++j)
-                U[AT(i, j)] = U[AT(i, j)] + (double)E[AT(i, j)] * inv;
+            for (int j = 1; j <= n; ++j) {
+                double corr = (double)E[AT(i, j)] * inv;
+                U[AT(i, j)] = U[AT(i, j)] + corr;
+                if (fabs(corr) > last_corr) last_corr = fabs(corr);
+            }
         ++outer;
     }
     orc_extract_f64(n, U, u);
     if (outer_out) *outer_out = outer;
     if (rel_out) *rel_out = rel;
+    if (corr_out) *corr_out = last_corr;
     free(U); free(r); free(E); free(R); free(F);
     return status;
 }

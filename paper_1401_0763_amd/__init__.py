@@ -45,6 +45,27 @@ class _Result(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _MixedDesc(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_void_p), ("boundary", ctypes.c_void_p),
+                ("rhs", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("rel_tol", ctypes.c_double), ("corr_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int64), ("inner_iters", ctypes.c_int64)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("u0", ctypes.c_void_p), ("boundary", ctypes.c_void_p),
+                ("rhs", ctypes.c_void_p), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("rel_tol", ctypes.c_double), ("corr_tol", ctypes.c_double),
+                ("max_outer", ctypes.c_int64), ("inner_iters", ctypes.c_int64)]
+
+
+class _RequestInfo(ctypes.Structure):
+    _fields_ = [("result", _Result), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 class _GridDesc(ctypes.Structure):
     _fields_ = [("u", ctypes.c_void_p), ("boundary", ctypes.c_void_p),
                 ("rhs", ctypes.c_void_p), ("n", ctypes.c_int32),
@@ -109,6 +130,25 @@ def _declare(lib):
     lib.sor_batch_solve_f64.restype = ctypes.c_int
     lib.sor_autotune.argtypes = [P, i32, i32, ctypes.POINTER(_Tiling)]
     lib.sor_autotune.restype = ctypes.c_int
+    lib.sor_batch_solve_mixed.argtypes = [P, ctypes.POINTER(_MixedDesc), i32, i32, P,
+                                          ctypes.POINTER(_Result)]
+    lib.sor_batch_solve_mixed.restype = ctypes.c_int
+    lib.sor_server_create.argtypes = [ctypes.c_int, i32, ctypes.c_size_t, i32, dbl,
+                                      ctypes.POINTER(P)]
+    lib.sor_server_create.restype = ctypes.c_int
+    lib.sor_server_submit.argtypes = [P, ctypes.POINTER(_Request),
+                                      ctypes.POINTER(ctypes.c_uint64)]
+    lib.sor_server_submit.restype = ctypes.c_int
+    lib.sor_server_poll.argtypes = [P, ctypes.c_uint64, dbl, ctypes.POINTER(_RequestInfo), P]
+    lib.sor_server_poll.restype = ctypes.c_int
+    lib.sor_server_clock.argtypes = [P]
+    lib.sor_server_clock.restype = dbl
+    lib.sor_server_stats.argtypes = [P] + [ctypes.POINTER(i64)] * 4
+    lib.sor_server_stats.restype = ctypes.c_int
+    lib.sor_server_last_error.argtypes = [P]
+    lib.sor_server_last_error.restype = ctypes.c_char_p
+    lib.sor_server_destroy.argtypes = [P]
+    lib.sor_server_destroy.restype = None
 
 
 def load_library():
@@ -350,3 +390,127 @@ def solve_mixed(u, boundary, rhs=None, omega=None, rel_tol=1e-10, max_outer=50,
     ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
     h = list(hbuf[: res.outer_steps + 1]) if hist else None
     return _result(st, res, h)
+
+
+@dataclass
+class MixedSpec:
+    """One grid of a mixed-precision batched solve (torch float64 CUDA tensors)."""
+    u: object
+    boundary: object
+    rhs: object = None
+    omega: float | None = None
+    rel_tol: float = 1e-10
+    corr_tol: float = 0.0
+    max_outer: int = 50
+    inner_iters: int = 0
+
+
+def batch_solve_mixed(specs, inner_bits=32, ctx: Context | None = None) -> list[Result]:
+    """Mixed-precision defect correction for many grids in one persistent launch."""
+    import torch
+    specs = list(specs)
+    if not specs:
+        return []
+    ctx = ctx or context(specs[0].u.device.index)
+    descs = (_MixedDesc * len(specs))()
+    for k, sp in enumerate(specs):
+        n = sp.u.shape[0]
+        d = descs[k]
+        d.u = _check_tensor("u", sp.u, torch.float64, (n, n))
+        d.boundary = _check_tensor("boundary", sp.boundary, torch.float64, (4 * n,))
+        d.rhs = None if sp.rhs is None else _check_tensor("rhs", sp.rhs, torch.float64, (n, n))
+        d.n = n
+        d.omega = (2.0 / (1.0 + math.sin(math.pi / (n + 1)))) if sp.omega is None else sp.omega
+        d.rel_tol = sp.rel_tol
+        d.corr_tol = sp.corr_tol
+        d.max_outer = sp.max_outer
+        d.inner_iters = sp.inner_iters
+    res = (_Result * len(specs))()
+    st = ctx.lib.sor_batch_solve_mixed(ctx.handle, descs, len(specs), int(inner_bits),
+                                       _stream_handle(specs[0].u), res)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    return [_result(r.status, r) for r in res]
+
+
+@dataclass
+class Completion:
+    ticket: int
+    status: int
+    result: Result
+    submit_s: float
+    admit_s: float
+    done_s: float
+    u: object                 # numpy n x n result
+
+
+class Server:
+    """Request loop of mixed-precision solves on one GPU (continuous batching).
+
+    Requests carry host (numpy) arrays; results come back as numpy arrays."""
+
+    def __init__(self, device=0, inner_bits=32, hbm_budget=8 << 30, max_slots=64,
+                 slice_ms=2.0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        st = self.lib.sor_server_create(int(device), int(inner_bits), int(hbm_budget),
+                                        int(max_slots), float(slice_ms), ctypes.byref(h))
+        if st != OK:
+            raise SorError(st, "sor_server_create failed")
+        self.handle = h
+        self._n = {}
+
+    def clock(self) -> float:
+        return self.lib.sor_server_clock(self.handle)
+
+    def submit(self, boundary, rhs=None, u0=None, omega=0.0, rel_tol=1e-8,
+               corr_tol=0.0, max_outer=50, inner_iters=0) -> int:
+        import numpy as np
+        b = np.ascontiguousarray(boundary, dtype=np.float64)
+        n = b.size // 4
+        f = None if rhs is None else np.ascontiguousarray(rhs, dtype=np.float64).reshape(n, n)
+        u = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).reshape(n, n)
+        r = _Request(None if u is None else u.ctypes.data, b.ctypes.data,
+                     None if f is None else f.ctypes.data, n, 0, float(omega),
+                     float(rel_tol), float(corr_tol), int(max_outer), int(inner_iters))
+        t = ctypes.c_uint64()
+        st = self.lib.sor_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        if st != OK:
+            raise SorError(st, "sor_server_submit failed")
+        self._n[t.value] = n
+        return t.value
+
+    def poll(self, ticket, wait_ms=0.0):
+        """Completion if the request finished, else None."""
+        import numpy as np
+        n = self._n[ticket]
+        info = _RequestInfo()
+        out = np.empty((n, n), dtype=np.float64)
+        st = self.lib.sor_server_poll(self.handle, ctypes.c_uint64(ticket), float(wait_ms),
+                                      ctypes.byref(info), out.ctypes.data)
+        if st == EBUSY:
+            return None
+        if st == EINVAL:
+            raise SorError(st, "unknown ticket")
+        del self._n[ticket]
+        return Completion(ticket, st, _result(st, info.result), info.submit_s,
+                          info.admit_s, info.done_s, out)
+
+    def stats(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        self.lib.sor_server_stats(self.handle, *[ctypes.byref(x) for x in v])
+        return dict(launches=v[0].value, completed=v[1].value, waiting=v[2].value,
+                    resident=v[3].value)
+
+    def error(self) -> str:
+        return self.lib.sor_server_last_error(self.handle).decode()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sor_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

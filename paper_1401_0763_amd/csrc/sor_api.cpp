@@ -340,6 +340,7 @@ void sor_ctx_destroy(sor_ctx *c) {
   (void)hipSetDevice(c->device);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   batch_state_free(c);
+  mix_state_free(c);
   for (DevBuf &b : c->bufs)
     if (b.p) (void)hipFree(b.p);
   if (c->host_ctl) (void)hipHostFree(c->host_ctl);

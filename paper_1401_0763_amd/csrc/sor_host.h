@@ -54,6 +54,7 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
                         const void *rhs, int32_t n, double omega);
 int prec_index(int bits);
 void batch_state_free(sor_ctx *c);
+void mix_state_free(sor_ctx *c);
 // Plain-solve tiling for a grid side: the autotuned entry of its size class,
 // else the context's tiling for the precision.
 sor_tiling tuned_tiling(sor_ctx *c, int prec, int n);

@@ -139,6 +139,8 @@ struct alignas(128) BQueue {
   int remaining;             // grids that still have queued work
   int error;                 // 1: a wait timed out
   long long deadline_ticks;  // wait limit in wall-clock ticks
+  long long t0;              // wall clock when the launch's first wave began
+  long long slice_ticks;     // > 0: grids pause after this long (time slice)
 };
 
 struct BItem {
@@ -158,6 +160,66 @@ __host__ __device__ inline int blocked_ntiles(int prec, int n, int T, int seg_ro
   const int CW = kLanes * V - 2 * A;
   return ((n + 1 + CW - 1) / CW) * ((n + 1 + seg_rows - 1) / seg_rows);
 }
+
+// Mixed-precision batched solves (FP64 defect correction around low-precision
+// sweeps).  Every grid cycles through four phases, each a set of work items:
+//   RESID   row blocks: FP64 residual r, partial sums of r^2, b^2 and max|r|
+//   CAST    row blocks: inner right-hand side fl(r * 2^p), zero inner iterate
+//   SWEEP   blocked-pass tiles of the inner solve (low precision)
+//   ACCUM   row blocks: u += e * 2^-p, partial max |correction|
+// The wave that completes a phase's last item runs the phase's serial step
+// (sums in a fixed order, stopping test, scale choice) and queues the next.
+enum MixPhase : int { kPhResid = 0, kPhCast = 1, kPhSweep = 2, kPhAccum = 3 };
+constexpr int kMixRows = 8;          // rows per row-block item
+
+struct alignas(128) BMGrid {
+  // Set by the host.
+  double *U;               // FP64 iterate (padded origin)
+  const double *F;         // h*h*f (padded origin) or nullptr
+  void *EA;                // inner iterate ping-pong (low precision, padded)
+  void *EB;
+  void *R;                 // inner right-hand side (low precision, padded)
+  double *partials;        // 3 doubles per row block
+  double *user_u;
+  const double *user_bdy;
+  const double *user_f;
+  int64_t pitch;           // FP64 grids
+  int64_t lo_pitch;        // low-precision grids
+  int32_t n;
+  int32_t T;               // inner iterations per blocked pass
+  int32_t seg_rows;
+  int32_t nrb;             // row blocks
+  double omega;
+  double rel_tol;          // stop when ||r||_2/||b||_2 <= rel_tol
+  double corr_tol;         // or when max |correction| < corr_tol (if > 0)
+  double target;           // scaling target of the inner right-hand side
+  int64_t max_outer;
+  int64_t inner_iters;
+  // Device state.
+  int32_t phase;
+  int32_t status;          // 0 running or paused, 1 converged, 2 limit, 3 non-finite
+  int32_t cur;             // inner iterate in EA (0) or EB (1)
+  int32_t pass_T;
+  int32_t nitems;          // items of the queued phase
+  int32_t scale_exp;
+  uint32_t items_done;
+  uint32_t nonfinite;      // an inner sweep stored a non-finite value
+  int64_t outer;           // corrections applied
+  int64_t inner_left;
+  int64_t inner_total;
+  int64_t passes;
+  double rel;              // latest relative residual
+  double rinf;
+  double last_corr;        // max |correction| of the latest correction
+};
+
+hipError_t launch_mix_pack(int prec_lo, const BMGrid *grids, const int *slots, int count,
+                           int max_n, hipStream_t s);
+hipError_t launch_mix_unpack(const BMGrid *grids, const int *slots, int count,
+                             int max_n, hipStream_t s);
+hipError_t launch_mix_batch(int prec_lo, BMGrid *grids, BQueue *q, BItem *ring,
+                            int waves, hipStream_t s);
+int mix_waves_per_cu(int prec_lo);
 
 hipError_t launch_batch_pack(const BGrid *grids, int count, int max_n,
                              hipStream_t s);

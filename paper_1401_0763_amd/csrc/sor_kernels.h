@@ -419,6 +419,64 @@ __global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
   report_pass<T>(ctl, sc, mx, T, bad, blockIdx.x % kSlots, gridDim.x);
 }
 
+// ---------------------------------------------------------------------------
+// Work queue of the persistent batched kernels (see BQueue / BItem).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish items (grid g, 0..ntiles-1) (whole wave).
+__device__ inline void bq_publish(BQueue *q, BItem *ring, int g, int ntiles) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long base = 0;
+  if (lane == 0)
+    base = __hip_atomic_fetch_add(&q->tail, (unsigned long long)ntiles,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  base = __shfl(base, 0, 64);
+  const unsigned long long gen = q->gen, mask = q->mask;
+  for (int i = lane; i < ntiles; i += 64) {
+    const unsigned long long idx = base + (unsigned long long)i;
+    BItem *it = &ring[idx & mask];
+    __hip_atomic_store(&it->payload, ((unsigned long long)g << 32) | (unsigned)i,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&it->tag, bq_tag(gen, idx), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Take the next item.  Returns false when no grid has work left (or a wait
+// exceeded the deadline, which raises q->error).  Every lane waits.
+__device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long idx = 0;
+  if (lane == 0)
+    idx = __hip_atomic_fetch_add(&q->head, 1ull, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+  idx = __shfl(idx, 0, 64);
+  BItem *it = &ring[idx & q->mask];
+  const unsigned long long want = bq_tag(q->gen, idx);
+  const long long t0 = wall_clock64();
+  for (;;) {
+    if (ld_acq(&it->tag) == want) break;
+    if (__hip_atomic_load(&q->remaining, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= 0)
+      return false;
+    if (__hip_atomic_load(&q->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return false;
+    if (wall_clock64() - t0 > q->deadline_ticks) {
+      if (lane == 0)
+        __hip_atomic_fetch_or(&q->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+  const unsigned long long p = __hip_atomic_load(&it->payload, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+  g = (int)(p >> 32);
+  tile = (int)(p & 0xffffffffu);
+  return true;
+}
+
 // Host-side launch of the blocked pass for one (precision, T); each pair is
 // instantiated in its own translation unit so the unrolled bodies compile in
 // parallel.

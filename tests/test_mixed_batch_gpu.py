@@ -1,0 +1,132 @@
+"""GPU parity of mixed-precision batched solves and of the request server.
+
+Each grid, whether solved in a batch or served among other requests, must
+equal the CPU oracle's defect-correction solve of that grid alone bit for bit
+at the same number of corrections (the inner sweeps, casts and corrections
+are exactly rounded; only the stopping test's norm sums differ in order)."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import omega_opt, poisson_manufactured, random_small
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sor():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_1401_0763_amd as m
+    return m
+
+
+@pytest.fixture()
+def ctx(sor):
+    c = sor.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return None if a is None else torch.tensor(np.ascontiguousarray(a), dtype=torch.float64,
+                                               device="cuda")
+
+
+def bitwise(a, b):
+    return np.array_equal(np.asarray(a).view(np.uint64), np.asarray(b).view(np.uint64))
+
+
+def grids_for(seed, sizes):
+    out = []
+    for k, n in enumerate(sizes):
+        g = random_small(seed * 100 + k, n, with_f=(k % 3 != 0), nonzero_u0=(k % 2 == 0))
+        if k % 4 == 1:
+            g = poisson_manufactured(n, seed=seed + k)
+        out.append(g)
+    return out
+
+
+@pytest.mark.parametrize("bits", [32, 16])
+def test_mixed_batch_fixed_corrections_bitwise(sor, ctx, bits):
+    grids = grids_for(1, [1, 4, 33, 64, 100, 130, 7, 250])
+    outer = 2
+    us = [dev(g.u0) for g in grids]
+    specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 0.0, outer, 0)
+             for u, g in zip(us, grids)]
+    res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
+    for k, (g, r, u) in enumerate(zip(grids, res, us)):
+        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, outer, bits, 2 * g.n)
+        assert r.outer_steps == ref.outer_steps == outer, (k, r)
+        assert bitwise(u.cpu().numpy(), ref.u), (k, g.n)
+        assert abs(r.rel_residual - ref.rel_residual) <= 1e-9 * ref.rel_residual + 1e-300
+
+
+@pytest.mark.parametrize("bits,tol", [(32, 1e-11), (16, 1e-9)])
+def test_mixed_batch_to_tolerance(sor, ctx, bits, tol):
+    grids = grids_for(2, [20, 63, 127, 90, 200])
+    us = [dev(g.u0) for g in grids]
+    specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), None, tol, 0.0, 40, 0)
+             for u, g in zip(us, grids)]
+    res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
+    for k, (g, r, u) in enumerate(zip(grids, res, us)):
+        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), tol, 40, bits, 2 * g.n)
+        assert ref.converged and r.converged, (k, r, ref.relhist)
+        assert r.outer_steps == ref.outer_steps, (k, r.outer_steps, ref.outer_steps)
+        assert r.rel_residual <= tol
+        assert bitwise(u.cpu().numpy(), ref.u), k
+
+
+def test_mixed_batch_correction_stop_rule(sor, ctx):
+    grids = grids_for(3, [40, 80, 120])
+    us = [dev(g.u0) for g in grids]
+    specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 1e-8, 30, 0)
+             for u, g in zip(us, grids)]
+    res = sor.batch_solve_mixed(specs, 32, ctx=ctx)
+    for k, (g, r, u) in enumerate(zip(grids, res, us)):
+        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, 30, 32, 2 * g.n, corr_tol=1e-8)
+        assert ref.converged and r.converged
+        assert r.outer_steps == ref.outer_steps
+        assert r.final_max_delta == ref.last_correction
+        assert bitwise(u.cpu().numpy(), ref.u), k
+
+
+@pytest.mark.parametrize("bits", [32, 16])
+def test_server_results_equal_standalone(sor, bits):
+    """A stream of requests through a small server (few slots, small memory
+    budget, short time slices, so requests wait, pause and resume): every
+    result equals the oracle's standalone solve bit for bit."""
+    rng = np.random.default_rng(7)
+    sizes = [int(rng.choice([16, 50, 100, 130, 200])) for _ in range(12)]
+    grids = [random_small(500 + k, n, with_f=True) for k, n in enumerate(sizes)]
+    tol = 1e-9 if bits == 32 else 1e-8
+    srv = sor.Server(0, inner_bits=bits, hbm_budget=24 << 20, max_slots=3, slice_ms=0.3)
+    try:
+        tickets = []
+        for g in grids:
+            tickets.append(srv.submit(g.bdy, g.f, None, 0.0, tol, 0.0, 40, 0))
+            time.sleep(0.002)
+        done = {}
+        t_end = time.time() + 120
+        while len(done) < len(tickets) and time.time() < t_end:
+            for t in tickets:
+                if t not in done:
+                    c = srv.poll(t, wait_ms=5.0)
+                    if c is not None:
+                        done[t] = c
+        assert len(done) == len(tickets), srv.stats()
+        st = srv.stats()
+        assert st["completed"] == len(tickets) and st["launches"] > 1, st
+    finally:
+        srv.close()
+    for t, g in zip(tickets, grids):
+        c = done[t]
+        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), tol, 40, bits,
+                           2 * g.n)
+        assert c.status == sor.OK and ref.converged, (g.n, c.result)
+        assert c.result.outer_steps == ref.outer_steps
+        assert bitwise(c.u, ref.u), g.n
+        assert c.submit_s <= c.admit_s <= c.done_s
