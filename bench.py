@@ -12,6 +12,19 @@ passes with device-side stopping checks, unpack).
 Output: one JSON line with GLUP/s (giga lattice-site updates per second), the
 dominant kernel's roofline position (algorithmic bytes per launch over the
 HIP-event-timed average launch), and the CPU oracle's rate on the host cores.
+Under "forms" the same line reports, each against plain one-grid-at-a-time
+FP64 on the same GPU:
+  mixed    4096^2 Poisson (f = N(0,1) + 2 pi^2 sin sin, seed 3): FP64 defect
+           correction around FP32 and binary16 inner sweeps vs plain FP64 SOR
+           to the same relative residual, errors against the exact discrete
+           solution (DST-I);
+  batched  512 grids, sides log-uniform in [64, 1024] (seed 4), f = N(0,1) on
+           odd grids, omega_opt, tol 1e-8: one persistent launch, FP64 and
+           FP32+refinement, solves/s;
+  serving  Poisson arrivals (seed 5) of requests with sides log-uniform in
+           [128, 2048], boundary U[0,100], f = N(0,1), each to relative
+           residual 1e-8 by FP32 + FP64 refinement through the request server,
+           at 0.7 x the server's saturated rate: p50/p99 latency and solves/s.
 """
 import argparse
 import json
@@ -78,6 +91,216 @@ def cpu_baseline(g, iters_k, seconds):
                       f"{dt:.1f} s"}
 
 
+def dst_exact(n, bdy, f):
+    """Exact discrete solution of the 5-point Dirichlet problem (DST-I)."""
+    import numpy as np
+    import scipy.fft
+    h = 1.0 / (n + 1)
+    b = h * h * np.asarray(f, dtype=np.float64).copy()
+    b[0, :] += bdy[0:n]
+    b[-1, :] += bdy[n:2 * n]
+    b[:, 0] += bdy[2 * n:3 * n]
+    b[:, -1] += bdy[3 * n:4 * n]
+    s2 = np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2
+    lam = 4.0 * (s2[:, None] + s2[None, :])
+    return scipy.fft.idstn(scipy.fft.dstn(b, type=1, norm="ortho") / lam, type=1,
+                           norm="ortho")
+
+
+def fp64_to_residual(sor, ctx, u, b, f, omega, rel_tol, chunk, max_iters, trace=None):
+    """Plain FP64 SOR from u, checking the relative residual every `chunk`
+    iterations; returns (iterations, rel).  trace, if a list, receives
+    (seconds, iterations, rel) after every chunk."""
+    its, rel = 0, float("inf")
+    t0 = time.perf_counter()
+    while its < max_iters:
+        sor.solve_f64(u, b, f, omega, 0.0, chunk, chunk, ctx=ctx)
+        its += chunk
+        sr, sb, _ = sor.residual_f64(u, b, f, ctx=ctx)
+        rel = math.sqrt(sr) / math.sqrt(sb) if sb > 0 else math.sqrt(sr)
+        if trace is not None:
+            trace.append((time.perf_counter() - t0, its, rel))
+        if rel <= rel_tol:
+            break
+    return its, rel
+
+
+def time_to(trace, target):
+    """First time in a (seconds, work, rel) trace at which rel <= target."""
+    for t, _, r in trace:
+        if r <= target:
+            return round(t, 3)
+    return None
+
+
+def form_mixed(sor, ctx, torch):
+    import numpy as np
+    from workloads import poisson_manufactured
+    n = 4096
+    g = poisson_manufactured(n, seed=3)
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    f = torch.tensor(g.f, dtype=torch.float64, device="cuda")
+    exact = dst_exact(n, g.bdy, g.f)
+    scale = float(np.max(np.abs(exact)))
+    targets = (1e-6, 1e-8, 1e-10)
+    out = {"workload": "poisson_manufactured_4096 (seed 3), omega_opt",
+           "note": "times to reach each relative residual; refinement step k is "
+                   "timed as k/steps of the whole run (every step does the same work)"}
+    for bits, max_outer in ((32, 9), (16, 4)):
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sor.solve_mixed(u, b, f, g.omega, 0.0, max_outer, bits, 2 * n, hist=True, ctx=ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = max(r.outer_steps, 1)
+        trace = [(dt * k / steps, k, float(x)) for k, x in enumerate(r.hist)]
+        err = float(np.max(np.abs(u.cpu().numpy() - exact))) / scale
+        out[f"fp{bits}_refine"] = {
+            "secs": round(dt, 3), "outer_steps": r.outer_steps,
+            "inner_iters_per_step": 2 * n,
+            "rel_history": [float(x) for x in r.hist],
+            "best_rel_residual": float(min(r.hist)),
+            "secs_to": {str(t): time_to(trace, t) for t in targets},
+            "max_err_vs_exact_rel": err}
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    trace = []
+    torch.cuda.synchronize()
+    fp64_to_residual(sor, ctx, u, b, f, g.omega, 1e-10, 2000, 40000, trace)
+    torch.cuda.synchronize()
+    err = float(np.max(np.abs(u.cpu().numpy() - exact))) / scale
+    out["fp64_plain"] = {"secs": round(trace[-1][0], 3), "iterations": trace[-1][1],
+                         "best_rel_residual": min(r for _, _, r in trace),
+                         "secs_to": {str(t): time_to(trace, t) for t in targets},
+                         "max_err_vs_exact_rel": err}
+    return out
+
+
+def form_batched(sor, ctx, torch):
+    from workloads import batch_grids
+    grids = batch_grids(512, 64, 1024, seed=4, tol=1e-8)
+    us = [torch.zeros((g.n, g.n), dtype=torch.float64, device="cuda") for g in grids]
+    bs = [torch.tensor(g.bdy, dtype=torch.float64, device="cuda") for g in grids]
+    fs = [None if g.f is None else torch.tensor(g.f, dtype=torch.float64, device="cuda")
+          for g in grids]
+    out = {"workload": "512 grids, n log-uniform [64,1024] (seed 4), tol 1e-8, check every 1"}
+
+    def timed(fn):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    specs = [sor.GridSpec(u, b, f, g.omega, 1e-8, 200000, 1)
+             for u, b, f, g in zip(us, bs, fs, grids)]
+    timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))           # records the graph
+    res, dt = timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))
+    lups = sum(g.n * g.n * r.iterations for g, r in zip(grids, res))
+    out["fp64_batched"] = {"secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
+                           "glups": round(lups / dt / 1e9, 1),
+                           "converged": sum(r.converged for r in res)}
+    mspecs = [sor.MixedSpec(u, b, f, g.omega, 0.0, 1e-8, 50, 0)
+              for u, b, f, g in zip(us, bs, fs, grids)]
+    timed(lambda: sor.batch_solve_mixed(mspecs, 32, ctx=ctx))
+    res, dt = timed(lambda: sor.batch_solve_mixed(mspecs, 32, ctx=ctx))
+    out["fp32_refine_batched"] = {"secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
+                                  "stop": "max |correction| < 1e-8",
+                                  "converged": sum(r.converged for r in res)}
+
+    def one_at_a_time():
+        its = 0
+        for u, b, f, g in zip(us, bs, fs, grids):
+            its += g.n * g.n * sor.solve_f64(u, b, f, g.omega, 1e-8, 200000, 1, ctx=ctx).iterations
+        return its
+    its, dt = timed(one_at_a_time)
+    out["fp64_one_at_a_time"] = {"secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
+                                 "glups": round(its / dt / 1e9, 1)}
+    out["speedup_batched_vs_one_at_a_time"] = round(
+        out["fp64_batched"]["solves_per_s"] / out["fp64_one_at_a_time"]["solves_per_s"], 2)
+    return out
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def form_serving(sor, ctx, torch, count, burst):
+    import numpy as np
+    from workloads import ServingStream
+    tol = 1e-8
+    srv = sor.Server(0, inner_bits=32, hbm_budget=64 << 30, max_slots=128, slice_ms=2.0)
+    try:
+        # Saturated rate: a closed-loop burst of `burst` requests.
+        probe = ServingStream(burst, 1.0, seed=55)
+        t0 = time.perf_counter()
+        ts = [srv.submit(*probe.request(k)[1:], None, 0.0, tol, 0.0, 50, 0) for k in range(burst)]
+        for t in ts:
+            while srv.poll(t, wait_ms=50.0) is None:
+                pass
+        sat = burst / (time.perf_counter() - t0)
+        rate = 0.7 * sat
+        stream = ServingStream(count, rate, seed=5)
+        lat, bad = [], 0
+        pending = {}
+        t0 = time.perf_counter()
+        k = 0
+        while k < count or pending:
+            now = time.perf_counter() - t0
+            while k < count and stream.arrivals[k] <= now:
+                n, bdy, f = stream.request(k)
+                t_sub = time.perf_counter() - t0
+                pending[srv.submit(bdy, f, None, 0.0, tol, 0.0, 50, 0)] = (stream.arrivals[k], t_sub)
+                k += 1
+            for t in list(pending):
+                c = srv.poll(t)
+                if c is not None:
+                    arr, t_sub = pending.pop(t)
+                    lat.append((c.done_s - c.submit_s) + (t_sub - arr))
+                    bad += c.status != sor.OK
+            time.sleep(0.0005)
+        makespan = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    served = {"requests": count, "rate_per_s": round(rate, 2),
+              "saturated_solves_per_s": round(sat, 2),
+              "solves_per_s": round(count / makespan, 2),
+              "p50_latency_ms": round(1e3 * percentile(lat, 50), 2),
+              "p99_latency_ms": round(1e3 * percentile(lat, 99), 2),
+              "not_converged": bad, "launches": st["launches"]}
+    # Baseline: the same arrivals through one-at-a-time plain FP64 (FIFO),
+    # relative residual checked every max(200, n) iterations.
+    lat0, its_total = [], 0
+    t0 = time.perf_counter()
+    for k in range(count):
+        n, bdy, f = stream.request(k)
+        now = time.perf_counter() - t0
+        if stream.arrivals[k] > now:
+            time.sleep(stream.arrivals[k] - now)
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        b = torch.tensor(bdy, dtype=torch.float64, device="cuda")
+        ff = torch.tensor(f, dtype=torch.float64, device="cuda")
+        its, rel = fp64_to_residual(sor, ctx, u, b, ff,
+                                    2.0 / (1.0 + math.sin(math.pi / (n + 1))), tol,
+                                    max(200, n), 40 * n)
+        _ = u.cpu()
+        lat0.append(time.perf_counter() - t0 - stream.arrivals[k])
+    span0 = time.perf_counter() - t0
+    base = {"solves_per_s": round(count / span0, 2),
+            "p50_latency_ms": round(1e3 * percentile(lat0, 50), 2),
+            "p99_latency_ms": round(1e3 * percentile(lat0, 99), 2)}
+    return {"workload": f"{count} requests, n log-uniform [128,2048] (seed 5), "
+                        "rel residual 1e-8, FP32 inner + FP64 refinement, "
+                        "HBM budget 64 GiB, 128 slots, 2 ms slices",
+            "served": served, "fp64_one_at_a_time_same_arrivals": base,
+            "speedup_solves_per_s": round(served["solves_per_s"] / base["solves_per_s"], 2),
+            "p99_ratio_baseline_over_served": round(base["p99_latency_ms"] / served["p99_latency_ms"], 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -89,6 +312,10 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="mixed,batched,serving",
+                    help="comma list of extra forms to measure, or 'none'")
+    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-burst", type=int, default=80)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one device-to-device copy of this "
                          "many MiB (a known-size reference for HBM counters)")
@@ -174,6 +401,18 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
         "bandwidth_equiv_GBs": round(glups * BYTES_PER_LUP_F64, 1),
     }
+    forms = [] if args.forms == "none" else args.forms.split(",")
+    line["forms"] = {}
+    if "mixed" in forms:
+        print("[bench] form: mixed precision 4096^2", file=sys.stderr, flush=True)
+        line["forms"]["mixed"] = form_mixed(sor, ctx, torch)
+    if "batched" in forms:
+        print("[bench] form: batched 512 grids", file=sys.stderr, flush=True)
+        line["forms"]["batched"] = form_batched(sor, ctx, torch)
+    if "serving" in forms:
+        print("[bench] form: serving", file=sys.stderr, flush=True)
+        line["forms"]["serving"] = form_serving(sor, ctx, torch, args.serve_requests,
+                                                args.serve_burst)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(g, K, args.cpu_seconds)

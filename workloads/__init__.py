@@ -16,7 +16,7 @@ Workloads (sizes are interior nodes per side; h = 1/(n+1)):
   * ``poisson_manufactured`` -- -lap u = f with f i.i.d. N(0,1) plus the
     manufactured term 2 pi^2 sin(pi x) sin(pi y), zero boundary.
   * ``batch_grids`` -- many grids with log-uniform side lengths.
-  * ``request_stream`` -- seeded Poisson arrivals of solve requests.
+  * ``ServingStream`` -- seeded Poisson arrivals of solve requests.
 """
 from __future__ import annotations
 
@@ -97,27 +97,6 @@ def batch_grids(count: int = 512, lo: int = 64, hi: int = 1024, seed: int = 4,
     return out
 
 
-@dataclass
-class Request:
-    arrival_s: float
-    grid: Grid
-
-
-def request_stream(count: int = 2000, rate_per_s: float = 100.0, lo: int = 128,
-                   hi: int = 2048, seed: int = 5, rel_tol: float = 1e-8) -> list[Request]:
-    """Poisson arrivals (exponential gaps at rate_per_s) of solve requests."""
-    rng = np.random.default_rng(seed)
-    t = 0.0
-    out = []
-    for k in range(count):
-        t += float(rng.exponential(1.0 / rate_per_s))
-        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
-        grid = random_grid(rng, n, with_f=True, tol=rel_tol)
-        grid.meta = {"index": k}
-        out.append(Request(t, grid))
-    return out
-
-
 def random_small(seed: int, n: int, with_f: bool = True, omega: float | None = None,
                  nonzero_u0: bool = False) -> Grid:
     """Small seeded grid for parity tests (random boundary, f, optional u0)."""
@@ -126,3 +105,36 @@ def random_small(seed: int, n: int, with_f: bool = True, omega: float | None = N
     f = rng.standard_normal((n, n)) * 1000.0 if with_f else None
     u0 = rng.uniform(0.0, 100.0, size=(n, n)) if nonzero_u0 else np.zeros((n, n))
     return Grid(n, u0, bdy, f, omega_opt(n) if omega is None else omega)
+
+
+class ServingStream:
+    """Seeded Poisson arrivals of solve requests, generated on demand.
+
+    Request k has side n = round(exp(U(ln lo, ln hi))), boundary values
+    U[0, 100] (4n, order north, south, west, east) and a source f that is an
+    n x n window, at a seeded offset, of one of a few pre-drawn hi x hi fields
+    of i.i.d. N(0, 1) values (so every f is itself i.i.d. N(0, 1) and no
+    request costs a fresh hi^2 draw).  Arrival gaps are exponential with mean
+    1/rate."""
+
+    def __init__(self, count=2000, rate_per_s=100.0, lo=128, hi=2048, seed=5,
+                 pool=4):
+        self.count, self.rate, self.lo, self.hi, self.seed = count, rate_per_s, lo, hi, seed
+        rng = np.random.default_rng([seed, 0])
+        self.pool = [rng.standard_normal((hi, hi)) for _ in range(pool)]
+        arr = np.random.default_rng([seed, 1])
+        gaps = arr.exponential(1.0 / rate_per_s, size=count)
+        self.arrivals = np.cumsum(gaps)
+        sz = np.random.default_rng([seed, 2])
+        self.sizes = [int(round(math.exp(x))) for x in
+                      sz.uniform(math.log(lo), math.log(hi), size=count)]
+
+    def request(self, k):
+        """(n, boundary, f) of request k."""
+        n = self.sizes[k]
+        rng = np.random.default_rng([self.seed, 3, k])
+        bdy = rng.uniform(0.0, 100.0, size=4 * n)
+        field = self.pool[k % len(self.pool)]
+        oi, oj = (int(x) for x in rng.integers(0, self.hi - n + 1, size=2))
+        f = np.ascontiguousarray(field[oi:oi + n, oj:oj + n])
+        return n, bdy, f
