@@ -288,8 +288,9 @@ sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
   if (rhs && (st = ensure(c, rf, bytes))) return st;
   T *A = origin<T>(c, ra, L), *B = origin<T>(c, rb, L);
   T *F = rhs ? origin<T>(c, rf, L) : nullptr;
-  HIP_TRY(c, launch_pack(prec, u, bdy, A, B, L.pitch, n, s));
-  if (rhs) HIP_TRY(c, launch_pack_rhs(prec, rhs, F, L.pitch, n, s));
+  unsigned *bad = &((Ctl *)c->bufs[kCtlBuf].p)->input_nonfinite;
+  HIP_TRY(c, launch_pack(prec, u, bdy, A, B, L.pitch, n, bad, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(prec, rhs, F, L.pitch, n, bad, s));
   *out = sor_result{};
   out->rel_residual = NAN;
   const Sched sc{max_iters, K, tol};
@@ -433,8 +434,8 @@ sor_status sor_residual_f64(sor_ctx *c, const double *u, const double *bdy,
   if ((st = ensure(c, kStats, 4 * sizeof(double)))) return st;
   double *U = origin<double>(c, kGridA64, L);
   double *F = rhs ? origin<double>(c, kF64Buf, L) : nullptr;
-  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, s));
-  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, s));
+  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, nullptr, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, nullptr, s));
   double *dstats = (double *)c->bufs[kStats].p;
   HIP_TRY(c, launch_residual(U, F, L.pitch, n, r, (double *)c->bufs[kPartials].p, dstats,
                              nullptr, kF32, 0, 0, s));
@@ -475,8 +476,8 @@ sor_status sor_solve_mixed(sor_ctx *c, double *u, const double *bdy, const doubl
   char *R = (char *)c->bufs[kLoRhs].p + Llo.origin_off() * prec_bytes(plo);
   double *dstats = (double *)c->bufs[kStats].p;
   double *partials = (double *)c->bufs[kPartials].p;
-  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, s));
-  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, s));
+  HIP_TRY(c, launch_pack(kF64, u, bdy, U, nullptr, L.pitch, n, nullptr, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, nullptr, s));
   // The inner right-hand side grid has a zero ring; only its interior changes.
   HIP_TRY(c, launch_fill_zero(plo, R, Llo.pitch, n, s));
 

@@ -129,16 +129,8 @@ __device__ __forceinline__ void batch_tile(BGrid *G, int tile, double (&mx)[kTMa
   v.nstrips = (v.n + 1 + CW - 1) / CW;
   v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
   v.omega = G->omega;
-  const int strip = tile % v.nstrips, seg = tile / v.nstrips;
-  const int j0 = strip * CW - A;
-  const int a = seg * v.seg_rows - S;
-  const int b = min(a + S + v.seg_rows, v.n + 1) + S;
-  const bool mask = (j0 < 1) || (j0 + kLanes * V - 1 > v.n) || (a < 1) || (b - 1 > v.n);
   ct m[T];
-  if (mask)
-    blocked_tile<P, T, POIS, true>(v, tile, m, bad);
-  else
-    blocked_tile<P, T, POIS, false>(v, tile, m, bad);
+  blocked_tile<P, T, POIS>(v, tile, m, bad);
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
 }
@@ -189,17 +181,21 @@ __global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BIte
 }
 
 // Pack every grid's caller arrays into its working grid A (and the ring into
-// B), and F = h*h*f.  Block (x, y): rows x*... of grid y.
-__global__ void batch_pack_kernel(const BGrid *grids, int count) {
-  const BGrid &G = grids[blockIdx.y];
+// B), and F = h*h*f.  Block (x, y): allocated row x - kMY of grid y; the
+// padding around the (n+2) x (n+2) grid is zeroed as well, since tile halos
+// read it.
+__global__ void batch_pack_kernel(BGrid *grids, int count) {
+  BGrid &G = grids[blockIdx.y];
   const int n = G.n;
-  const int r = blockIdx.x;                 // row 0 .. n+1
-  if (r > n + 1) return;
+  const int r = (int)blockIdx.x - kMY;
+  if (r > n + 1 + kMY) return;
   double *A = (double *)G.A, *B = (double *)G.B;
   double *F = (double *)G.F;
   const double h = 1.0 / (double)(n + 1);
   const double h2 = h * h;
-  for (int c = threadIdx.x; c <= n + 1; c += blockDim.x) {
+  bool ok = true;
+  for (int64_t ca = threadIdx.x; ca < G.pitch; ca += blockDim.x) {
+    const int c = (int)ca - kMX;
     const bool in_r = r >= 1 && r <= n, in_c = c >= 1 && c <= n;
     double val = 0.0;
     if (in_r && in_c) val = G.user_u[(int64_t)(r - 1) * n + (c - 1)];
@@ -210,8 +206,14 @@ __global__ void batch_pack_kernel(const BGrid *grids, int count) {
     const int64_t o = (int64_t)r * G.pitch + c;
     A[o] = val;
     if (!(in_r && in_c)) B[o] = val;
-    if (F) F[o] = (in_r && in_c) ? h2 * G.user_f[(int64_t)(r - 1) * n + (c - 1)] : 0.0;
+    ok = ok && __builtin_isfinite(val);
+    if (F) {
+      const double fv = (in_r && in_c) ? h2 * G.user_f[(int64_t)(r - 1) * n + (c - 1)] : 0.0;
+      F[o] = fv;
+      ok = ok && __builtin_isfinite(fv);
+    }
   }
+  if (!ok) G.nonfinite = 1u;      // sweeps detect only values turning non-finite
 }
 
 __global__ void batch_unpack_kernel(const BGrid *grids, int count) {
@@ -224,8 +226,9 @@ __global__ void batch_unpack_kernel(const BGrid *grids, int count) {
     G.user_u[(int64_t)(r - 1) * n + c] = S[(int64_t)r * G.pitch + c + 1];
 }
 
-hipError_t launch_batch_pack(const BGrid *grids, int count, int max_n, hipStream_t s) {
-  hipLaunchKernelGGL(batch_pack_kernel, dim3(max_n + 2, count), dim3(256), 0, s, grids, count);
+hipError_t launch_batch_pack(BGrid *grids, int count, int max_n, hipStream_t s) {
+  hipLaunchKernelGGL(batch_pack_kernel, dim3(max_n + 2 + 2 * kMY, count), dim3(256), 0, s,
+                     grids, count);
   return hipGetLastError();
 }
 

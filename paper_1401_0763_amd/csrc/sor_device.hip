@@ -77,7 +77,8 @@ __global__ void ctl_reset_kernel(Ctl *ctl) {
   for (int k = t; k < kHistCap; k += blockDim.x) ctl->hist[k] = 0.0;
   if (t == 0) {
     ctl->counter = 0;
-    ctl->nonfinite = 0;
+    ctl->nonfinite = ctl->input_nonfinite;   // inputs packed for this solve
+    ctl->input_nonfinite = 0;
     ctl->stop = 0;
     ctl->it_base = 0;
     ctl->stop_iter = 0;
@@ -88,14 +89,22 @@ __global__ void ctl_reset_kernel(Ctl *ctl) {
   }
 }
 
+// The set-up kernels below cover a grid's whole allocation: rows -kMY ..
+// n+1+kMY and every column of the pitch, relative to the origin.  Cells off
+// the (n+2) x (n+2) grid are set to 0, so the tiles' halo loads (which reach
+// into this padding) only ever see finite values, whatever the memory held
+// before.  Launch: one block row per allocated row, x over the pitch.
+
 // Embed u (n*n) and the boundary edges (north, south, west, east) into the
-// working grid A; the boundary ring also goes to B (the ping-pong partner).
+// working grid A; the boundary ring and the padding also go to B (the
+// ping-pong partner).
 template <typename st>
 __global__ void pack_kernel(const st *u, const st *bdy, st *A, st *B,
-                            int64_t pitch, int n) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;   // 0 .. n+1
-  const int r = blockIdx.y;                              // 0 .. n+1
-  if (c > n + 1) return;
+                            int64_t pitch, int n, unsigned *bad) {
+  const int64_t ca = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= pitch) return;
+  const int c = (int)ca - kMX;
+  const int r = (int)blockIdx.y - kMY;
   const bool in_r = r >= 1 && r <= n, in_c = c >= 1 && c <= n;
   st val = (st)0;
   if (in_r && in_c) val = u[(int64_t)(r - 1) * n + (c - 1)];
@@ -106,20 +115,23 @@ __global__ void pack_kernel(const st *u, const st *bdy, st *A, st *B,
   const int64_t o = (int64_t)r * pitch + c;
   A[o] = val;
   if (B && !(in_r && in_c)) B[o] = val;
+  if (bad && !__builtin_isfinite(val)) *bad = 1u;
 }
 
-// F = h*h*f on the interior, 0 on the ring; the product is formed in double
+// F = h*h*f on the interior, 0 elsewhere; the product is formed in double
 // and rounded once to the storage type.
 template <typename st>
 __global__ void pack_rhs_kernel(const st *f, st *F, int64_t pitch, int n,
-                                double h2) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c > n + 1) return;
+                                double h2, unsigned *bad) {
+  const int64_t ca = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= pitch) return;
+  const int c = (int)ca - kMX;
+  const int r = (int)blockIdx.y - kMY;
   st val = (st)0;
   if (r >= 1 && r <= n && c >= 1 && c <= n)
     val = (st)(h2 * (double)f[(int64_t)(r - 1) * n + (c - 1)]);
   F[(int64_t)r * pitch + c] = val;
+  if (bad && !__builtin_isfinite(val)) *bad = 1u;
 }
 
 template <typename st>
@@ -132,10 +144,10 @@ __global__ void unpack_kernel(const st *A, st *u, int64_t pitch, int n) {
 
 template <typename st>
 __global__ void fill_zero_kernel(st *A, int64_t pitch, int n) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int r = blockIdx.y;
-  if (c > n + 1) return;
-  A[(int64_t)r * pitch + c] = (st)0;
+  const int64_t ca = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ca >= pitch) return;
+  const int r = (int)blockIdx.y - kMY;
+  A[(int64_t)r * pitch + (ca - kMX)] = (st)0;
 }
 
 // ---------------------------------------------------------------------------
@@ -264,31 +276,34 @@ hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t s) {
   return hipGetLastError();
 }
 
-static dim3 ring_grid(int n) { return dim3((n + 2 + 255) / 256, n + 2); }
+// One block row per allocated row (n + 2 + 2*kMY), x over the pitch.
+static dim3 alloc_grid(int64_t pitch, int n) {
+  return dim3((unsigned)((pitch + 255) / 256), (unsigned)(n + 2 + 2 * kMY));
+}
 
 hipError_t launch_pack(int prec, const void *u, const void *bdy, void *A,
-                       void *B, int64_t pitch, int n, hipStream_t s) {
+                       void *B, int64_t pitch, int n, unsigned *bad, hipStream_t s) {
   switch (prec) {
-    case kF64: hipLaunchKernelGGL(pack_kernel<double>, ring_grid(n), dim3(256), 0, s,
+    case kF64: hipLaunchKernelGGL(pack_kernel<double>, alloc_grid(pitch, n), dim3(256), 0, s,
                                   (const double *)u, (const double *)bdy, (double *)A,
-                                  (double *)B, pitch, n); break;
-    case kF32: hipLaunchKernelGGL(pack_kernel<float>, ring_grid(n), dim3(256), 0, s,
+                                  (double *)B, pitch, n, bad); break;
+    case kF32: hipLaunchKernelGGL(pack_kernel<float>, alloc_grid(pitch, n), dim3(256), 0, s,
                                   (const float *)u, (const float *)bdy, (float *)A,
-                                  (float *)B, pitch, n); break;
+                                  (float *)B, pitch, n, bad); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_pack_rhs(int prec, const void *f, void *F, int64_t pitch, int n,
-                           hipStream_t s) {
+                           unsigned *bad, hipStream_t s) {
   const double h = 1.0 / (double)(n + 1);
   const double h2 = h * h;
   switch (prec) {
-    case kF64: hipLaunchKernelGGL(pack_rhs_kernel<double>, ring_grid(n), dim3(256), 0, s,
-                                  (const double *)f, (double *)F, pitch, n, h2); break;
-    case kF32: hipLaunchKernelGGL(pack_rhs_kernel<float>, ring_grid(n), dim3(256), 0, s,
-                                  (const float *)f, (float *)F, pitch, n, h2); break;
+    case kF64: hipLaunchKernelGGL(pack_rhs_kernel<double>, alloc_grid(pitch, n), dim3(256), 0, s,
+                                  (const double *)f, (double *)F, pitch, n, h2, bad); break;
+    case kF32: hipLaunchKernelGGL(pack_rhs_kernel<float>, alloc_grid(pitch, n), dim3(256), 0, s,
+                                  (const float *)f, (float *)F, pitch, n, h2, bad); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -309,11 +324,11 @@ hipError_t launch_unpack(int prec, const void *A, void *u, int64_t pitch, int n,
 
 hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t s) {
   switch (prec) {
-    case kF64: hipLaunchKernelGGL(fill_zero_kernel<double>, ring_grid(n), dim3(256), 0, s,
+    case kF64: hipLaunchKernelGGL(fill_zero_kernel<double>, alloc_grid(pitch, n), dim3(256), 0, s,
                                   (double *)A, pitch, n); break;
-    case kF32: hipLaunchKernelGGL(fill_zero_kernel<float>, ring_grid(n), dim3(256), 0, s,
+    case kF32: hipLaunchKernelGGL(fill_zero_kernel<float>, alloc_grid(pitch, n), dim3(256), 0, s,
                                   (float *)A, pitch, n); break;
-    case kF16: hipLaunchKernelGGL(fill_zero_kernel<_Float16>, ring_grid(n), dim3(256), 0, s,
+    case kF16: hipLaunchKernelGGL(fill_zero_kernel<_Float16>, alloc_grid(pitch, n), dim3(256), 0, s,
                                   (_Float16 *)A, pitch, n); break;
     default: return hipErrorInvalidValue;
   }

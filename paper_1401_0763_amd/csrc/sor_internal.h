@@ -49,9 +49,9 @@ Layout make_layout(int n, int prec);
 struct alignas(256) Ctl {
   unsigned long long slots[kSlots][kTMax];  // bit patterns of non-negative doubles
   unsigned int counter;     // wavefronts finished in the running pass
-  unsigned int nonfinite;   // sticky: a stored value was NaN or infinite
+  unsigned int nonfinite;   // sticky: a value became NaN or infinite
   int stop;                 // 0 running, 1 converged, 2 non-finite
-  int pad0;
+  unsigned int input_nonfinite;  // set by packing when an input is not finite
   long long it_base;        // iterations completed by finished passes
   long long stop_iter;      // iteration whose check passed
   double stop_max;
@@ -203,7 +203,7 @@ struct alignas(128) BMGrid {
   int32_t nitems;          // items of the queued phase
   int32_t scale_exp;
   uint32_t items_done;
-  uint32_t nonfinite;      // an inner sweep stored a non-finite value
+  uint32_t nonfinite;      // an inner sweep produced a non-finite value
   int64_t outer;           // corrections applied
   int64_t inner_left;
   int64_t inner_total;
@@ -221,7 +221,7 @@ hipError_t launch_mix_batch(int prec_lo, BMGrid *grids, BQueue *q, BItem *ring,
                             int waves, hipStream_t s);
 int mix_waves_per_cu(int prec_lo);
 
-hipError_t launch_batch_pack(const BGrid *grids, int count, int max_n,
+hipError_t launch_batch_pack(BGrid *grids, int count, int max_n,
                              hipStream_t s);
 hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n,
                                hipStream_t s);
@@ -238,10 +238,12 @@ BlockGeom block_geom(int prec, int T);
 
 // ----------------------------- launchers ----------------------------------
 hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t s);
+// Packing sets *bad (when bad is not null) if an input value is not finite.
 hipError_t launch_pack(int prec, const void *u, const void *bdy, void *gridA,
-                       void *gridB, int64_t pitch, int n, hipStream_t s);
+                       void *gridB, int64_t pitch, int n, unsigned *bad,
+                       hipStream_t s);
 hipError_t launch_pack_rhs(int prec, const void *f, void *F, int64_t pitch,
-                           int n, hipStream_t s);
+                           int n, unsigned *bad, hipStream_t s);
 hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
                          int n, hipStream_t s);
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,

@@ -16,10 +16,6 @@
 #ifndef SOR_PREFETCH
 #define SOR_PREFETCH 4
 #endif
-// Register-window periods unrolled per loop iteration of the row walk.
-#ifndef SOR_UNROLL
-#define SOR_UNROLL 1
-#endif
 
 namespace sor {
 
@@ -48,29 +44,23 @@ __device__ __forceinline__ void static_for(F &&f) {
 }
 
 // ---------------------------------------------------------------------------
-// Cross-lane moves.  DPP wave_shr:1 hands every lane the value of the lane
-// below it (lane i receives lane i-1); wave_shl:1 the lane above.  Lanes at
-// the wave edge receive 0 (bound_ctrl); they only ever feed halo cells.
+// Cross-lane moves through the LDS crossbar (ds_bpermute): lane i receives
+// the value of lane src.  The permute's completion is tracked by the LDS
+// counter like any LDS read, so it needs no hand-placed wait states.  (In
+// this sweep the DPP wave shifts, which use no LDS bandwidth, produced
+// lane-dependent results that varied between runs when their source had just
+// been written by an FP64 operation, so they are not used.)  The wave-edge
+// lanes receive the value from the opposite edge; they only feed halo cells.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int dpp_from_left_i(int x) {
-  return __builtin_amdgcn_mov_dpp(x, 0x138, 0xf, 0xf, true);
+__device__ __forceinline__ int lane_permute(int addr, int x) {
+  return __builtin_amdgcn_ds_bpermute(addr, x);
 }
-__device__ __forceinline__ int dpp_from_right_i(int x) {
-  return __builtin_amdgcn_mov_dpp(x, 0x130, 0xf, 0xf, true);
+__device__ __forceinline__ float lane_permute(int addr, float x) {
+  return __int_as_float(lane_permute(addr, __float_as_int(x)));
 }
-__device__ __forceinline__ float from_left(float x) {
-  return __int_as_float(dpp_from_left_i(__float_as_int(x)));
-}
-__device__ __forceinline__ float from_right(float x) {
-  return __int_as_float(dpp_from_right_i(__float_as_int(x)));
-}
-__device__ __forceinline__ double from_left(double x) {
-  return __hiloint2double(dpp_from_left_i(__double2hiint(x)),
-                          dpp_from_left_i(__double2loint(x)));
-}
-__device__ __forceinline__ double from_right(double x) {
-  return __hiloint2double(dpp_from_right_i(__double2hiint(x)),
-                          dpp_from_right_i(__double2loint(x)));
+__device__ __forceinline__ double lane_permute(int addr, double x) {
+  return __hiloint2double(lane_permute(addr, __double2hiint(x)),
+                          lane_permute(addr, __double2loint(x)));
 }
 
 __device__ __forceinline__ double wave_max(double x) {
@@ -123,11 +113,19 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
     if (anybad)
       __hip_atomic_fetch_or(&ctl->nonfinite, 1u, __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_AGENT);
-    prev = __hip_atomic_fetch_add(&ctl->counter, 1u, __ATOMIC_ACQ_REL,
+    // The finishing wave reads only the slots and the flag, which are
+    // device-scope atomics: waiting for them to complete orders them before
+    // the counter.  An agent-scope release here would write back this XCD's
+    // whole L2 once per wave; the grid itself is published at the kernel's
+    // end.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    prev = __hip_atomic_fetch_add(&ctl->counter, 1u, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   }
   prev = __shfl(prev, 0, 64);
   if (prev != waves_total - 1) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
   // Last wave of the pass: gather the slots (lane s reads slot s).
   double it_max[T];
@@ -220,8 +218,14 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 // this same step, row q-1 after stage k-1 updated it one step earlier, and
 // row q's own other-colour cells at level k-1, so every update sees exactly
 // the values the two-phase iteration of Algorithm 1 gives it.  Rows live in a
-// rotating register window; horizontal neighbours in the adjacent lane arrive
-// by DPP.
+// rotating register window.
+//
+// All stages of one step update cells of the same parity v0 within a lane,
+// and the one neighbour that lies in the adjacent lane (left of cell 0 when
+// v0 = 0, right of cell V-1 when v0 = 1) is a cell that stage k-1 updated one
+// step earlier.  So every update sends that edge value across lanes at once
+// (xn[k+1]), and the exchange has a whole step to complete before stage k+1
+// uses it; stage 0's value comes from the next, not yet updated, row.
 //
 // Values near the strip and segment edges depend on cells outside the tile
 // and are wrong after enough stages (the dependency cone grows one cell per
@@ -230,20 +234,20 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 // output are separate grids (ping-pong), so halos are read at the pass's
 // starting level whatever order tiles run in.
 //
-// The step loop runs in chunks of W steps with no branch inside a chunk, so
-// the compiler can overlap the stages of neighbouring steps: loads read a
-// clamped row (always inside the tile's rows), stores of rows outside the
-// core are dropped by an out-of-range offset, and the per-iteration maxima
-// weight each change by 1 (core row) or 0 (halo row).  MASK tiles touch the
-// boundary ring or lie partly outside the grid; their boundary and
-// out-of-grid cells keep their value through a select.  Other tiles hold
-// interior cells only and need no mask.
+// One branch-free body serves every tile.  Boundary and out-of-grid cells
+// must keep their value; they get a relaxation factor of 0 instead of omega
+// (u + 0*(g - u) = u for finite g): per lane for columns, and per window slot
+// for rows, where each slot also carries the weight (1 for core rows, 0 for
+// halo rows) of its changes in the maxima.  Loads read a clamped row (always
+// inside the tile's rows) and stores of non-core rows are dropped through an
+// out-of-range offset.
 //
 // m[t] receives the largest |u' - u| of iteration t over the tile's core
-// cells (0 in halo lanes); bad is set if a stored interior value is not
-// finite.
+// cells (0 in halo lanes).  A non-finite value first appears, from finite
+// operands, as an infinity whose change is infinite, so bad is set when some
+// maximum is not finite (non-finite inputs are caught when they are packed).
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS, bool MASK>
+template <int P, int T, bool POIS>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
                                              bool &bad) {
@@ -255,7 +259,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   constexpr int WV = kLanes * V;
   constexpr int CW = WV - 2 * A;
   constexpr int D = SOR_PREFETCH;                // rows prefetched ahead
-  constexpr int W = ((S + D + 2) + 1) & ~1;      // window rows (even)
+  constexpr int W = ((S + D + 2) + 1) / 2 * 2;   // window rows (even)
   constexpr int ESZ = (int)sizeof(st);
 
   const int lane = threadIdx.x & 63;
@@ -272,10 +276,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   const int rhi = min(core1, n + 1);
   const bool lane_core = (lane * V >= A) && (lane * V < WV - A);
   const bool lane_store = lane_core && (col0 <= n) && (col0 + V - 1 >= 1);
-  bool ok[V];
+  ct omc[V];                                     // omega, or 0 off the interior
 #pragma unroll
-  for (int v = 0; v < V; ++v) ok[v] = (col0 + v >= 1) && (col0 + v <= n);
-  const ct om = (ct)g.omega;
+  for (int v = 0; v < V; ++v)
+    omc[v] = (col0 + v >= 1 && col0 + v <= n) ? (ct)g.omega : (ct)0;
   const unsigned rowbytes = (unsigned)(g.pitch * ESZ);
   const unsigned extent = (unsigned)(b - a) * rowbytes;     // < 2^31
   const int64_t tile_off = (int64_t)a * g.pitch + j0;
@@ -285,104 +289,114 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   if constexpr (POIS) rf = make_rsrc((const st *)g.F + tile_off, extent);
   const unsigned lane_off = (unsigned)(lane * V * ESZ);
   const unsigned st_off = lane_store ? lane_off : kDrop;
+  const int from_lo = ((lane + 63) & 63) << 2;   // permute address: lane - 1
+  const int from_hi = ((lane + 1) & 63) << 2;    // permute address: lane + 1
 
-  ct w[W][V];
-  ct fw[POIS ? W : 1][V];
+  ct w[W][V];                                    // row window
+  ct fw[POIS ? W : 1][V];                        // h*h*f of the window rows
+  ct wc[W];                                      // slot weight in the maxima
+  ct wr[W];                                      // 1 for interior rows, else 0
 #pragma unroll
-  for (int s = 0; s < W; ++s)
+  for (int s = 0; s < W; ++s) {
+    wc[s] = (ct)0;
+    wr[s] = (ct)0;
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       w[s][v] = (ct)0;
       if constexpr (POIS) fw[s][v] = (ct)0;
     }
+  }
 #pragma unroll
   for (int t = 0; t < T; ++t) m[t] = (ct)0;
 
-  // Prologue: rows a .. a+D+1 into slots 0 .. D+1 (b - a >= 2S + 1 > D + 2).
+  // Row rn (clamped to the tile) into window slot SP, with its attributes.
+  auto load_row = [&](int rn, auto SP) __attribute__((always_inline)) {
+    constexpr int sp = decltype(SP)::value;
+    wc[sp] = (rn >= rlo && rn < rhi) ? (ct)1 : (ct)0;
+    wr[sp] = (rn >= 1 && rn <= n) ? (ct)1 : (ct)0;
+    const unsigned soff = (unsigned)(min(rn, b - 1) - a) * rowbytes;
+    const Vec<P> x = buf_load<P>(rin, lane_off, soff);
 #pragma unroll
-  for (int s = 0; s < D + 2; ++s) {
-    const Vec<P> x = buf_load<P>(rin, lane_off, (unsigned)s * rowbytes);
-#pragma unroll
-    for (int v = 0; v < V; ++v) w[s][v] = (ct)x.v[v];
+    for (int v = 0; v < V; ++v) w[sp][v] = (ct)x.v[v];
     if constexpr (POIS) {
-      const Vec<P> y = buf_load<P>(rf, lane_off, (unsigned)s * rowbytes);
+      const Vec<P> y = buf_load<P>(rf, lane_off, soff);
 #pragma unroll
-      for (int v = 0; v < V; ++v) fw[s][v] = (ct)y.v[v];
+      for (int v = 0; v < V; ++v) fw[sp][v] = (ct)y.v[v];
     }
-  }
+  };
+  // Prologue: rows a .. a+D+1 into slots 0 .. D+1 (b - a >= 2S + 1 > D + 2).
+  static_for<0, D + 2>([&](auto SP) __attribute__((always_inline)) {
+    load_row(a + decltype(SP)::value, SP);
+  });
 
-  const int nsteps = b - a - 2;                  // steps r = a+1 .. b-2
-  constexpr int CH = W * SOR_UNROLL;             // steps per loop iteration
-  for (int base = 0; base < nsteps; base += CH) {
-    static_for<0, CH>([&](auto I) __attribute__((always_inline)) {
+  // Cross-lane neighbour of stage k at the coming step (see above).  At the
+  // first step (v0 = 1) stage 0 needs the right neighbour of cell V-1 of row
+  // a+1 (slot 1), i.e. cell 0 of the lane above; deeper stages start on rows
+  // above the tile, whose values never reach core cells.
+  ct xs[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) xs[k] = (ct)0;
+  xs[0] = lane_permute(from_hi, w[1][0]);
+
+  // Steps r = a+1 .. b-2 in chunks of W, so window slots are static.
+  const int nsteps = b - a - 2;
+  for (int base = 0; base < nsteps; base += W) {
+    static_for<0, W>([&](auto I) __attribute__((always_inline)) {
       constexpr int i = decltype(I)::value;
       const int r = a + 1 + base + i;
-      // Prefetch row r+D+1 (clamped to the tile) into its slot ((row-a) mod W).
-      {
-        constexpr int sp = (i + D + 2) % W;
-        const int rp = min(r + D + 1, b - 1);
-        const unsigned soff = (unsigned)(rp - a) * rowbytes;
-        const Vec<P> x = buf_load<P>(rin, lane_off, soff);
-#pragma unroll
-        for (int v = 0; v < V; ++v) w[sp][v] = (ct)x.v[v];
-        if constexpr (POIS) {
-          const Vec<P> y = buf_load<P>(rf, lane_off, soff);
-#pragma unroll
-          for (int v = 0; v < V; ++v) fw[sp][v] = (ct)y.v[v];
-        }
-      }
-      // Stages: k-th half-sweep on row r-k.
+      load_row(r + D + 1, std::integral_constant<int, (i + D + 2) % W>{});
+      // Cells of colour k&1 in this lane at stage k: (q + col0 + v + k) even,
+      // and q + k = r has the parity of 1 + i because a, base and W are even.
+      constexpr int v0 = (1 + i) & 1;
+      // Edge cell whose value the next step's stages need from this lane.
+      constexpr int ve = v0 == 1 ? V - 1 : 0;
+      const int to = v0 == 1 ? from_lo : from_hi;
+      ct xn[S];
+      // Stage 0 of the next step updates row r+1, still at level 0 here; its
+      // exchange goes first, since it is the first one used.
+      xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
+      // Stage k (half-sweep k) on row r-k.
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
         constexpr int sq = ((i + 1 - k) % W + W) % W;
         constexpr int su = (sq + W - 1) % W;
         constexpr int sd = (sq + 1) % W;
-        // Cells of colour k&1 in this lane: (q + col0 + v + k) even, and
-        // q + k has the parity of 1 + i because a, base and W are even.
-        constexpr int v0 = (1 + i) & 1;
-        const int q = r - k;
-        const ct cnt = (q >= rlo && q < rhi) ? (ct)1 : (ct)0;        // uniform
-        const bool row_upd = (q >= 1) && (q <= n);                   // uniform
-        static_for<0, V / 2>([&](auto J) __attribute__((always_inline)) {
-          constexpr int v = v0 + 2 * decltype(J)::value;
+        static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
+          constexpr int v = v0 + 2 * decltype(JV)::value;
           const ct self = w[sq][v];
-          ct left, right;
-          if constexpr (v == 0) left = from_left(w[sq][V - 1]);
-          else left = w[sq][v - 1];
-          if constexpr (v == V - 1) right = from_right(w[sq][0]);
-          else right = w[sq][v + 1];
+          const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
+          const ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
           ct s = (w[su][v] + w[sd][v]) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
           const ct gs = (ct)0.25 * s;
-          ct nu = self + om * (gs - self);
+          ct nu = self + (omc[v] * wr[sq]) * (gs - self);
           if constexpr (P == kF16) nu = (ct)(st)nu;
-          if constexpr (MASK) nu = (row_upd && ok[v]) ? nu : self;
           const ct d = vabs(nu - self);
           w[sq][v] = nu;
-          m[k >> 1] = vmax(m[k >> 1], d * cnt);
+          m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
+          if constexpr (v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
+        // Keep the exchange where it is issued (a scheduler would otherwise
+        // sink it next to its use a step later and wait for it there).
+        __builtin_amdgcn_sched_barrier(0);
       });
-      // Row r-S+1 has now had all S half-sweeps: store it if it is core.
-      {
-        constexpr int so = ((i + 2 - S) % W + W) % W;
-        const int qo = r - S + 1;
-        const bool row_ok = (qo >= rlo) && (qo < rhi);
-        Vec<P> x;
-        bool nf = false;
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          x.v[v] = (st)w[so][v];
-          nf = nf | (ok[v] && !__builtin_isfinite(w[so][v]));
-        }
-        bad = bad | (nf && row_ok && lane_store);
-        buf_store<P>(x, rout, st_off | (row_ok ? 0u : kDrop),
-                     row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
-      }
+      for (int k = 0; k < S; ++k) xs[k] = xn[k];
+      // Row r-S+1 has had all S half-sweeps: store it if it is a core row.
+      constexpr int so = ((i + 2 - S) % W + W) % W;
+      const int qo = r - S + 1;
+      const bool row_ok = (qo >= rlo) && (qo < rhi);
+      Vec<P> x;
+#pragma unroll
+      for (int v = 0; v < V; ++v) x.v[v] = (st)w[so][v];
+      buf_store<P>(x, rout, st_off | (row_ok ? 0u : kDrop),
+                   row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
     });
   }
-  if (!lane_core) {
 #pragma unroll
-    for (int t = 0; t < T; ++t) m[t] = (ct)0;
+  for (int t = 0; t < T; ++t) {
+    if (!lane_core) m[t] = (ct)0;
+    bad = bad | !__builtin_isfinite(m[t]);
   }
 }
 
@@ -395,23 +409,9 @@ __global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
   if (ctl && ctl_stopped(ctl)) return;
   using ct = typename PT<P>::ct;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  constexpr int V = PT<P>::V;
-  constexpr int S = 2 * T;
-  constexpr int A = ((S + V - 1) / V) * V;
-  constexpr int CW = kLanes * V - 2 * A;
-  // A tile needs masking if its loaded rows or columns reach the boundary
-  // ring or beyond (rows a..b-1, columns j0..j0+64V-1).
-  const int strip = tile % g.nstrips, seg = tile / g.nstrips;
-  const int j0 = strip * CW - A;
-  const int a = seg * g.seg_rows - S;
-  const int b = min(a + S + g.seg_rows, g.n + 1) + S;
-  const bool mask = (j0 < 1) || (j0 + kLanes * V - 1 > g.n) || (a < 1) || (b - 1 > g.n);
   ct m[T];
   bool bad = false;
-  if (mask)
-    blocked_tile<P, T, POIS, true>(g, tile, m, bad);
-  else
-    blocked_tile<P, T, POIS, false>(g, tile, m, bad);
+  blocked_tile<P, T, POIS>(g, tile, m, bad);
   if (!ctl) return;
   double mx[T];
 #pragma unroll

@@ -111,17 +111,9 @@ __device__ __forceinline__ bool mix_sweep_tile(BMGrid *G, int tile) {
   v.nstrips = (v.n + 1 + CW - 1) / CW;
   v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
   v.omega = G->omega;
-  const int strip = tile % v.nstrips, seg = tile / v.nstrips;
-  const int j0 = strip * CW - A;
-  const int a = seg * v.seg_rows - S;
-  const int b = min(a + S + v.seg_rows, v.n + 1) + S;
-  const bool mask = (j0 < 1) || (j0 + kLanes * V - 1 > v.n) || (a < 1) || (b - 1 > v.n);
   ct m[T];
   bool bad = false;
-  if (mask)
-    blocked_tile<PL, T, true, true>(v, tile, m, bad);
-  else
-    blocked_tile<PL, T, true, false>(v, tile, m, bad);
+  blocked_tile<PL, T, true>(v, tile, m, bad);
   return bad;
 }
 
@@ -241,19 +233,23 @@ __global__ __launch_bounds__(64) void mix_batch_kernel(BMGrid *grids, BQueue *q,
   }
 }
 
-// Pack the listed grids: U (and its ring), F = h*h*f, zero rings of EA, EB, R.
+// Pack the listed grids: U (and its ring), F = h*h*f, zero rings of EA, EB,
+// R.  Block (x, y): allocated row x - kMY of listed grid y; the padding
+// around each (n+2) x (n+2) grid is zeroed as well, since tile halos read it.
 template <int PL>
 __global__ void mix_pack_kernel(const BMGrid *grids, const int *slots, int count) {
   using st = typename PT<PL>::st;
   const BMGrid &G = grids[slots[blockIdx.y]];
   const int n = G.n;
-  const int r = blockIdx.x;
-  if (r > n + 1) return;
+  const int r = (int)blockIdx.x - kMY;
+  if (r > n + 1 + kMY) return;
   const double h = 1.0 / (double)(n + 1);
   const double h2 = h * h;
   double *F = const_cast<double *>(G.F);
-  for (int c = threadIdx.x; c <= n + 1; c += blockDim.x) {
-    const bool in_r = r >= 1 && r <= n, in_c = c >= 1 && c <= n;
+  const bool in_r = r >= 1 && r <= n;
+  for (int64_t ca = threadIdx.x; ca < G.pitch; ca += blockDim.x) {
+    const int c = (int)ca - kMX;
+    const bool in_c = c >= 1 && c <= n;
     double val = 0.0;
     if (in_r && in_c) val = G.user_u[(int64_t)(r - 1) * n + (c - 1)];
     else if (r == 0 && in_c) val = G.user_bdy[c - 1];
@@ -262,12 +258,14 @@ __global__ void mix_pack_kernel(const BMGrid *grids, const int *slots, int count
     else if (c == n + 1 && in_r) val = G.user_bdy[3 * n + r - 1];
     G.U[(int64_t)r * G.pitch + c] = val;
     if (F) F[(int64_t)r * G.pitch + c] = (in_r && in_c) ? h2 * G.user_f[(int64_t)(r - 1) * n + (c - 1)] : 0.0;
-    if (!(in_r && in_c)) {
-      const int64_t lc = (int64_t)r * G.lo_pitch + c;
-      ((st *)G.EA)[lc] = (st)0;
-      ((st *)G.EB)[lc] = (st)0;
-      ((st *)G.R)[lc] = (st)0;
-    }
+  }
+  for (int64_t ca = threadIdx.x; ca < G.lo_pitch; ca += blockDim.x) {
+    const int c = (int)ca - kMX;
+    if (in_r && c >= 1 && c <= n) continue;
+    const int64_t lc = (int64_t)r * G.lo_pitch + c;
+    ((st *)G.EA)[lc] = (st)0;
+    ((st *)G.EB)[lc] = (st)0;
+    ((st *)G.R)[lc] = (st)0;
   }
 }
 
@@ -283,10 +281,10 @@ __global__ void mix_unpack_kernel(const BMGrid *grids, const int *slots, int cou
 hipError_t launch_mix_pack(int prec_lo, const BMGrid *grids, const int *slots, int count,
                            int max_n, hipStream_t s) {
   if (prec_lo == kF32)
-    hipLaunchKernelGGL(mix_pack_kernel<kF32>, dim3(max_n + 2, count), dim3(256), 0, s, grids,
+    hipLaunchKernelGGL(mix_pack_kernel<kF32>, dim3(max_n + 2 + 2 * kMY, count), dim3(256), 0, s, grids,
                        slots, count);
   else
-    hipLaunchKernelGGL(mix_pack_kernel<kF16>, dim3(max_n + 2, count), dim3(256), 0, s, grids,
+    hipLaunchKernelGGL(mix_pack_kernel<kF16>, dim3(max_n + 2 + 2 * kMY, count), dim3(256), 0, s, grids,
                        slots, count);
   return hipGetLastError();
 }
