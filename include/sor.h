@@ -106,13 +106,26 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
 
 /* Tiling of the blocked kernel for one storage precision (64, 32 or 16 bits):
  * iters_per_pass in {1, 2, 3, 4, 6} (iterations applied per HBM pass) and seg_rows, the
- * rows of output per wavefront (even, 8..1024).  0 in a field means "keep". */
+ * rows of output per wavefront (even, 8..1024).  0 in a field means "keep".
+ * A new context uses iters_per_pass 6 and reports seg_rows 0: until seg_rows
+ * is set, each plain solve picks it from the grid side, so that a pass has
+ * about as many tiles as the device holds resident wavefronts of the pass
+ * kernel (4*2*iters_per_pass..768 rows); batched solves use 64 rows below
+ * n = 512, else 192 (FP64) or 96.  An autotuned entry for the grid's size
+ * class (sor_autotune) takes precedence over both. */
 typedef struct sor_tiling {
     int32_t iters_per_pass;
     int32_t seg_rows;
 } sor_tiling;
 sor_status sor_ctx_set_tiling(sor_ctx *ctx, int32_t bits, const sor_tiling *t);
 sor_status sor_ctx_get_tiling(const sor_ctx *ctx, int32_t bits, sor_tiling *t);
+/* The tiling a plain solve of a grid with side n at this precision would use
+ * now (autotuned entry, else the context's tiling with seg_rows resolved from
+ * n); has_rhs != 0 for a Poisson solve (its kernel holds fewer resident
+ * wavefronts).  Host-side query (may ask the runtime for the kernel's
+ * occupancy); EINVAL for a null argument, bad bits or n outside 1..65536. */
+sor_status sor_ctx_tiling_for(sor_ctx *ctx, int32_t bits, int32_t n, int32_t has_rhs,
+                              sor_tiling *t);
 
 /* Kernel timing for measurement.  While profiling is on, every sweep-kernel
  * launch of the plain and mixed solves is bracketed by HIP events on the

@@ -115,6 +115,8 @@ def _declare(lib):
     lib.sor_ctx_set_tiling.restype = ctypes.c_int
     lib.sor_ctx_get_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
     lib.sor_ctx_get_tiling.restype = ctypes.c_int
+    lib.sor_ctx_tiling_for.argtypes = [P, i32, i32, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_ctx_tiling_for.restype = ctypes.c_int
     solve_args = [P, P, P, P, i32, dbl, dbl, i64, i64, P,
                   ctypes.POINTER(_Result), P]
     for name in ("sor_solve_f64", "sor_solve_f32"):
@@ -227,8 +229,16 @@ class Context:
         return t.iters_per_pass, t.seg_rows
 
     def get_tiling(self, bits: int) -> tuple[int, int]:
+        """The context's tiling; seg_rows 0 means chosen per grid size."""
         t = _Tiling()
         self._check(self.lib.sor_ctx_get_tiling(self.handle, int(bits), ctypes.byref(t)))
+        return t.iters_per_pass, t.seg_rows
+
+    def tiling_for(self, bits: int, n: int, has_rhs: bool = False) -> tuple[int, int]:
+        """The (iters_per_pass, seg_rows) a plain solve of side n would use."""
+        t = _Tiling()
+        self._check(self.lib.sor_ctx_tiling_for(self.handle, int(bits), int(n),
+                                                int(bool(has_rhs)), ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
 
 

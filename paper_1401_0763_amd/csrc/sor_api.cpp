@@ -158,7 +158,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       void **result_grid) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
-  const sor_tiling tl = tuned_tiling(c, prec, L.n);
+  const sor_tiling tl = tuned_tiling(c, prec, L.n, F != nullptr);
   const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega);
@@ -399,6 +399,17 @@ sor_status sor_ctx_get_tiling(const sor_ctx *c, int32_t bits, sor_tiling *t) {
   const int p = prec_index(bits);
   if (p < 0) return SOR_EINVAL;
   *t = c->tiling[p];
+  return SOR_OK;
+}
+
+sor_status sor_ctx_tiling_for(sor_ctx *c, int32_t bits, int32_t n, int32_t has_rhs,
+                              sor_tiling *t) {
+  if (!c || !t) return SOR_EINVAL;
+  const int p = prec_index(bits);
+  if (p < 0) return fail(c, SOR_EINVAL, "bits must be 64, 32 or 16");
+  if (n < 1 || n > kMaxN) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN);
+  if (hipSetDevice(c->device) != hipSuccess) return fail(c, SOR_EDEVICE, "hipSetDevice failed");
+  *t = tuned_tiling(c, p, n, has_rhs != 0);
   return SOR_OK;
 }
 

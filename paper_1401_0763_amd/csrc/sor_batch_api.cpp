@@ -55,16 +55,14 @@ void batch_state_free(sor_ctx *c) {
 // Size class of a grid side: nearest half power of two (so 64, 90, 128, ...).
 int size_class(int n) { return (int)std::lround(2.0 * std::log2((double)std::max(n, 1))); }
 
-// Tiling for a grid of side n at precision prec: the autotuned entry of its
-// class if there is one, else the context's tiling for large grids and a
-// shallower, shorter tile for small ones (which have few tiles per pass).
-sor_tiling tiling_for(sor_ctx *c, int prec, int n) {
+sor_tiling batch_tiling(sor_ctx *c, int prec, int n) {
   if (c->batch) {
     auto &m = c->batch->tune[prec];
     auto it = m.find(size_class(n));
     if (it != m.end()) return it->second;
   }
   sor_tiling t = c->tiling[prec];
+  if (t.seg_rows == 0) t.seg_rows = n < 512 ? 64 : (prec == kF64 ? 192 : 96);
   if (n < 512) {
     t.iters_per_pass = std::min(t.iters_per_pass, 4);
     t.seg_rows = std::min(t.seg_rows, 64);
@@ -72,13 +70,39 @@ sor_tiling tiling_for(sor_ctx *c, int prec, int n) {
   return t;
 }
 
-sor_tiling tuned_tiling(sor_ctx *c, int prec, int n) {
+int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
+  if (c->cus <= 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess || cus <= 0)
+      cus = 256;
+    c->cus = cus;
+  }
+  int &occ = c->occ[prec][T][pois ? 1 : 0];
+  if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, T, pois));
+  const BlockGeom gm = block_geom(prec, T);
+  const long long strips = (n + 1 + gm.CW - 1) / gm.CW;
+  const long long slots = (long long)occ * c->cus;
+  const int lo = 4 * gm.S, hi = 768;
+  int seg = hi;
+  for (int k = 1; k <= 64; ++k) {
+    const long long segs = std::max(1LL, k * slots / strips);
+    seg = (int)((n + 1 + segs - 1) / segs);
+    seg += seg & 1;
+    if (seg <= hi) break;
+  }
+  return std::min(hi, std::max(lo, seg));
+}
+
+sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {
   if (c->batch) {
     auto &m = c->batch->tune[prec];
     auto it = m.find(size_class(n));
     if (it != m.end()) return it->second;
   }
-  return c->tiling[prec];
+  sor_tiling t = c->tiling[prec];
+  if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, prec, n, t.iters_per_pass, pois);
+  return t;
 }
 
 void clear_tuning(sor_ctx *c, int prec) {
@@ -164,7 +188,7 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
     offA[g] = arena; arena += bytes;
     offB[g] = arena; arena += bytes;
     if (grids[g].rhs) { offF[g] = arena; arena += bytes; }
-    til[g] = tiling_for(c, kF64, n);
+    til[g] = batch_tiling(c, kF64, n);
     til[g].iters_per_pass = batch_T(til[g].iters_per_pass);
     const int T0 = (int)batch_depth_host(grids[g].max_iters, til[g].iters_per_pass);
     total_items += blocked_ntiles(kF64, n, T0, til[g].seg_rows);
@@ -331,11 +355,11 @@ sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
   HIP_TRY(c, hipEventCreate(&e0));
   HIP_TRY(c, hipEventCreate(&e1));
   const Sched sc{1, 1, 0.0};
-  sor_tiling bt{c->tiling[prec].iters_per_pass, c->tiling[prec].seg_rows};
+  sor_tiling bt = tuned_tiling(c, prec, n, false);
   double best_t = INFINITY;
   hipError_t e = hipSuccess;
   for (int T : {1, 2, 3, 4, 6}) {
-    for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384}) {
+    for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768}) {
       if (seg > 2 * (n + 1) && seg != 16) continue;
       GridView v;
       v.in = A; v.out = B; v.F = nullptr; v.pitch = L.pitch; v.n = n;

@@ -4,4 +4,5 @@
 namespace sor {
 template hipError_t launch_blocked_PT<kF32, 4>(const GridView &, Ctl *,
                                               const Sched &, hipStream_t);
+template int blocked_blocks_per_cu<kF32, 4>(bool);
 }  // namespace sor

@@ -338,7 +338,8 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
 // The blocked passes are instantiated in the sor_blocked_*_t*.hip units.
 #define SOR_EXTERN_BLOCKED(P, T)                                               \
   extern template hipError_t launch_blocked_PT<P, T>(                          \
-      const GridView &, Ctl *, const Sched &, hipStream_t);
+      const GridView &, Ctl *, const Sched &, hipStream_t);                    \
+  extern template int blocked_blocks_per_cu<P, T>(bool);
 #define SOR_EXTERN_BLOCKED_ALL(P)                                              \
   SOR_EXTERN_BLOCKED(P, 1) SOR_EXTERN_BLOCKED(P, 2) SOR_EXTERN_BLOCKED(P, 3)   \
   SOR_EXTERN_BLOCKED(P, 4) SOR_EXTERN_BLOCKED(P, 6)
@@ -357,6 +358,27 @@ static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
     case 6: return launch_blocked_PT<P, 6>(v, ctl, sc, s);
   }
   return hipErrorInvalidValue;
+}
+
+template <int P>
+static int blocked_blocks_per_cu_P(int T, bool pois) {
+  switch (T) {
+    case 1: return blocked_blocks_per_cu<P, 1>(pois);
+    case 2: return blocked_blocks_per_cu<P, 2>(pois);
+    case 3: return blocked_blocks_per_cu<P, 3>(pois);
+    case 4: return blocked_blocks_per_cu<P, 4>(pois);
+    case 6: return blocked_blocks_per_cu<P, 6>(pois);
+  }
+  return 0;
+}
+
+int blocked_blocks_per_cu(int prec, int T, bool pois) {
+  switch (prec) {
+    case kF64: return blocked_blocks_per_cu_P<kF64>(T, pois);
+    case kF32: return blocked_blocks_per_cu_P<kF32>(T, pois);
+    case kF16: return blocked_blocks_per_cu_P<kF16>(T, pois);
+  }
+  return 0;
 }
 
 bool blocked_T_supported(int T) {

@@ -34,7 +34,7 @@ struct sor_ctx {
   int device = 0;
   std::string err;
   int kernel = SOR_KERNEL_BLOCKED;
-  sor_tiling tiling[3] = {{4, 192}, {4, 96}, {4, 96}};  // by precision
+  sor_tiling tiling[3] = {{6, 0}, {6, 0}, {6, 0}};  // by precision; seg 0: by size
   sor::DevBuf bufs[sor::kNumRoles];
   sor::Ctl *host_ctl = nullptr;                        // pinned mirror
   double *host_stats = nullptr;                        // pinned [4]
@@ -43,6 +43,8 @@ struct sor_ctx {
   double prof_ms = 0.0;
   int64_t prof_launches = 0;
   sor::BatchState *batch = nullptr;                    // batched-solve state
+  int cus = 0;                                         // compute units (lazy)
+  int occ[3][7][2] = {};                               // pass blocks per CU (lazy)
 };
 
 namespace sor {
@@ -55,9 +57,20 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
 int prec_index(int bits);
 void batch_state_free(sor_ctx *c);
 void mix_state_free(sor_ctx *c);
-// Plain-solve tiling for a grid side: the autotuned entry of its size class,
-// else the context's tiling for the precision.
-sor_tiling tuned_tiling(sor_ctx *c, int prec, int n);
+// Segment rows chosen from the grid side for one plain solve: as many tiles
+// as the pass kernel has resident wavefront slots on the device (or a whole
+// multiple of that when a single round would need segments above 768 rows),
+// and at least 4*2T rows so the 2*2T halo rows stay a modest overhead.
+int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois);
+// Tiling of a plain solve of side n: the autotuned entry of its size class if
+// there is one, else the context's tiling with seg_rows from auto_seg_rows
+// when none was set.
+sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois);
+// Tiling of one grid inside a batched launch (many grids share the chip, so
+// a grid's own tile count does not need to fill it): the autotuned entry, else
+// the context's tiling with 64 rows below n = 512 and 192 (FP64) or 96 rows
+// above when none was set.
+sor_tiling batch_tiling(sor_ctx *c, int prec, int n);
 void clear_tuning(sor_ctx *c, int prec);
 
 }  // namespace sor

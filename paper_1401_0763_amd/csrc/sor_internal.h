@@ -254,6 +254,8 @@ hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s);
 bool blocked_T_supported(int T);
+// Pass-kernel workgroups (wavefronts) resident per CU; 0 if the query fails.
+int blocked_blocks_per_cu(int prec, int T, bool pois);
 // Simple kernel: one launch per colour, in place on v.in (v.out ignored).
 hipError_t launch_simple_iteration(int prec, const GridView &v, Ctl *ctl,
                                    const Sched &sc, hipStream_t s);

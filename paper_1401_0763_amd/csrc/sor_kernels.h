@@ -493,4 +493,16 @@ hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
   return hipGetLastError();
 }
 
+// Wavefronts of the pass kernel (one per workgroup) that one CU holds at once.
+template <int P, int T>
+int blocked_blocks_per_cu(bool pois) {
+  int nb = 0;
+  const hipError_t e =
+      pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &nb, reinterpret_cast<const void *>(&blocked_pass_kernel<P, T, true>), 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &nb, reinterpret_cast<const void *>(&blocked_pass_kernel<P, T, false>), 64, 0);
+  return e == hipSuccess ? nb : 0;
+}
+
 }  // namespace sor

@@ -34,7 +34,6 @@
 
 namespace sor {
 
-sor_tiling tuned_tiling(sor_ctx *c, int prec, int n);
 
 namespace {
 
@@ -290,7 +289,7 @@ extern "C" sor_status sor_batch_solve_mixed(sor_ctx *c, const sor_mixed_desc *gr
     lay[g] = slot_layout(grids[g].n, plo, grids[g].rhs != nullptr, false);
     off[g] = arena;
     arena += lay[g].total;
-    til[g] = tuned_tiling(c, plo == kF32 ? kF32 : kF16, grids[g].n);
+    til[g] = batch_tiling(c, plo == kF32 ? kF32 : kF16, grids[g].n);
     size_t most = (size_t)lay[g].nrb;
     for (int t : {1, 2, 4})
       most = std::max(most, (size_t)blocked_ntiles(plo, grids[g].n, t, til[g].seg_rows));
@@ -535,7 +534,7 @@ void sor_server::loop() {
       step(hipMemcpyAsync(du, q->u0.data(), q->u0.size() * 8, hipMemcpyHostToDevice, s));
       step(hipMemcpyAsync(db, q->bdy.data(), q->bdy.size() * 8, hipMemcpyHostToDevice, s));
       if (df) step(hipMemcpyAsync(df, q->f.data(), q->f.size() * 8, hipMemcpyHostToDevice, s));
-      sor_tiling t = tuned_tiling(ctx, prec_lo, q->n);
+      sor_tiling t = batch_tiling(ctx, prec_lo, q->n);
       t.seg_rows = std::max(t.seg_rows, kServerMinSeg);
       fill_slot(run.h_grids[q->slot], region, q->lay, prec_lo, q->n, du, db, df, q->omega,
                 q->rel_tol, q->corr_tol, q->max_outer, q->inner_iters, t);
