@@ -130,7 +130,8 @@ __device__ __forceinline__ void batch_tile(BGrid *G, int tile, double (&mx)[kTMa
   v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
   v.omega = G->omega;
   ct m[T];
-  blocked_tile<P, T, POIS>(v, tile, m, bad);
+  // Tiles of this grid's next pass may run on other XCDs in this same launch.
+  blocked_tile<P, T, POIS, kCohAgent>(v, tile, m, bad);
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
 }
@@ -172,8 +173,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BIte
         if (anybad)
           __hip_atomic_fetch_or(&G->nonfinite, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      prev = __hip_atomic_fetch_add(&G->tiles_done, 1u, __ATOMIC_ACQ_REL,
-                                    __HIP_MEMORY_SCOPE_AGENT);
+      prev = count_item_done(&G->tiles_done);   // grid stores are device-scope
     }
     prev = __shfl(prev, 0, 64);
     if (prev == (unsigned)G->ntiles - 1) batch_grid_finish<P>(G, g, q, ring);

@@ -184,25 +184,33 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base,
                                            (int)kRsrcWord3);
 }
 
-template <int P>
+// Cache policy of the sweep's grid accesses.  kCohDefault: cached in the
+// XCD's L2 (visibility to other XCDs comes with the kernel's end).  kCohAgent:
+// device-scope loads and stores (the form of relaxed agent-scope atomic
+// accesses), for kernels whose wavefronts read, in the same launch, cells
+// that wavefronts on other XCDs wrote.
+constexpr int kCohDefault = 0;
+constexpr int kCohAgent = 16;      // SC1
+
+template <int P, int AUX = kCohDefault>
 __device__ __forceinline__ Vec<P> buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff,
                                            unsigned soff) {
   if constexpr (sizeof(Vec<P>) == 16) {
-    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, AUX));
   } else {
-    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    return __builtin_bit_cast(Vec<P>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
   }
 }
 
-template <int P>
+template <int P, int AUX = kCohDefault>
 __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_t r,
                                           unsigned voff, unsigned soff) {
   if constexpr (sizeof(Vec<P>) == 16) {
     using v4 = unsigned __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4, x), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4, x), r, (int)voff, (int)soff, AUX);
   } else {
     using v2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, x), r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, x), r, (int)voff, (int)soff, AUX);
   }
 }
 
@@ -247,7 +255,7 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 // operands, as an infinity whose change is infinite, so bad is set when some
 // maximum is not finite (non-finite inputs are caught when they are packed).
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS>
+template <int P, int T, bool POIS, int COH = kCohDefault>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
                                              bool &bad) {
@@ -315,11 +323,11 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     wc[sp] = (rn >= rlo && rn < rhi) ? (ct)1 : (ct)0;
     wr[sp] = (rn >= 1 && rn <= n) ? (ct)1 : (ct)0;
     const unsigned soff = (unsigned)(min(rn, b - 1) - a) * rowbytes;
-    const Vec<P> x = buf_load<P>(rin, lane_off, soff);
+    const Vec<P> x = buf_load<P, COH>(rin, lane_off, soff);
 #pragma unroll
     for (int v = 0; v < V; ++v) w[sp][v] = (ct)x.v[v];
     if constexpr (POIS) {
-      const Vec<P> y = buf_load<P>(rf, lane_off, soff);
+      const Vec<P> y = buf_load<P, COH>(rf, lane_off, soff);
 #pragma unroll
       for (int v = 0; v < V; ++v) fw[sp][v] = (ct)y.v[v];
     }
@@ -389,7 +397,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       Vec<P> x;
 #pragma unroll
       for (int v = 0; v < V; ++v) x.v[v] = (st)w[so][v];
-      buf_store<P>(x, rout, st_off | (row_ok ? 0u : kDrop),
+      buf_store<P, COH>(x, rout, st_off | (row_ok ? 0u : kDrop),
                    row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
     });
   }
@@ -417,6 +425,44 @@ __global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
   report_pass<T>(ctl, sc, mx, T, bad, blockIdx.x % kSlots, gridDim.x);
+}
+
+// Device-scope scalar loads and stores (relaxed agent-scope atomics, i.e.
+// accesses that bypass a stale or dirty copy in one XCD's L2), for grid data
+// that persistent kernels hand from one wavefront to another in one launch.
+__device__ __forceinline__ double ld_agent(const double *p) {
+  return __longlong_as_double(__hip_atomic_load(reinterpret_cast<const long long *>(p),
+                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_agent(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<long long *>(p), __double_as_longlong(v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ld_agent(const float *p) {
+  return __int_as_float(__hip_atomic_load(reinterpret_cast<const int *>(p),
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_agent(float *p, float v) {
+  __hip_atomic_store(reinterpret_cast<int *>(p), __float_as_int(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ _Float16 ld_agent(const _Float16 *p) {
+  return __builtin_bit_cast(_Float16, __hip_atomic_load(reinterpret_cast<const short *>(p),
+                                                        __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void st_agent(_Float16 *p, _Float16 v) {
+  __hip_atomic_store(reinterpret_cast<short *>(p), __builtin_bit_cast(short, v),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Count one finished work item whose device-scope stores must be visible to
+// the wave that sees the count complete: wait for them, then a relaxed
+// increment (an agent-scope release would also write back this XCD's L2).
+__device__ __forceinline__ unsigned count_item_done(unsigned *counter) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);
+  return __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------

@@ -29,13 +29,15 @@ __device__ __forceinline__ void mix_resid_cell(const BMGrid &G, int i, int j,
   const double *U = G.U;
   const int64_t p = G.pitch;
   const int64_t c = (int64_t)i * p + j;
-  const double s = (U[c - p] + U[c + p]) + (U[c - 1] + U[c + 1]);
+  const double un = ld_agent(U + c - p), us = ld_agent(U + c + p);
+  const double uw = ld_agent(U + c - 1), ue = ld_agent(U + c + 1);
+  const double s = (un + us) + (uw + ue);
   const double t = G.F ? G.F[c] + s : s;
-  r = t - 4.0 * U[c];
-  const double nb = (i == 1) ? U[c - p] : 0.0;
-  const double sb = (i == G.n) ? U[c + p] : 0.0;
-  const double wb = (j == 1) ? U[c - 1] : 0.0;
-  const double eb = (j == G.n) ? U[c + 1] : 0.0;
+  r = t - 4.0 * ld_agent(U + c);
+  const double nb = (i == 1) ? un : 0.0;
+  const double sb = (i == G.n) ? us : 0.0;
+  const double wb = (j == 1) ? uw : 0.0;
+  const double eb = (j == G.n) ? ue : 0.0;
   const double bs = (nb + sb) + (wb + eb);
   b = G.F ? G.F[c] + bs : bs;
 }
@@ -72,13 +74,13 @@ __device__ void mix_rowblock(BMGrid *G, int t, int phase) {
         double r, b;
         mix_resid_cell(*G, i, j, r, b);
         const int64_t lc = (int64_t)i * G->lo_pitch + j;
-        R[lc] = to_lo<PL>(ldexp(r, pexp));
-        EA[lc] = (st)0;
+        st_agent(R + lc, to_lo<PL>(ldexp(r, pexp)));
+        st_agent(EA + lc, (st)0);
       } else {
         const int64_t lc = (int64_t)i * G->lo_pitch + j;
-        const double corr = (double)(float)E[lc] * inv;
+        const double corr = (double)(float)ld_agent(E + lc) * inv;
         const int64_t c = (int64_t)i * G->pitch + j;
-        G->U[c] = G->U[c] + corr;
+        st_agent(G->U + c, ld_agent(G->U + c) + corr);
         a2 = fmax(a2, fabs(corr));
       }
     }
@@ -87,9 +89,9 @@ __device__ void mix_rowblock(BMGrid *G, int t, int phase) {
   a1 = wave_sum(a1);
   a2 = wave_max(a2);
   if (lane == 0) {
-    G->partials[3 * t + 0] = a0;
-    G->partials[3 * t + 1] = a1;
-    G->partials[3 * t + 2] = a2;
+    st_agent(G->partials + 3 * t + 0, a0);
+    st_agent(G->partials + 3 * t + 1, a1);
+    st_agent(G->partials + 3 * t + 2, a2);
   }
 }
 
@@ -113,7 +115,9 @@ __device__ __forceinline__ bool mix_sweep_tile(BMGrid *G, int tile) {
   v.omega = G->omega;
   ct m[T];
   bool bad = false;
-  blocked_tile<PL, T, true>(v, tile, m, bad);
+  // The next pass's tiles and the ACCUM phase may run on other XCDs in this
+  // same launch.
+  blocked_tile<PL, T, true, kCohAgent>(v, tile, m, bad);
   return bad;
 }
 
@@ -226,8 +230,7 @@ __global__ __launch_bounds__(64) void mix_batch_kernel(BMGrid *grids, BQueue *q,
       mix_rowblock<PL>(G, item, phase);
     }
     unsigned prev = 0;
-    if (lane == 0)
-      prev = __hip_atomic_fetch_add(&G->items_done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) prev = count_item_done(&G->items_done);   // grid data is device-scope
     prev = __shfl(prev, 0, 64);
     if (prev == (unsigned)G->nitems - 1) mix_finish<PL>(G, g, q, ring);
   }
