@@ -19,14 +19,19 @@ its running maximum) over the HIP-event-timed kernel time, against the
 non-fused FP64 vector rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), with the
 HBM-equivalent bandwidth (16 algorithmic bytes per update) and the
 counter-measured traffic beside it.
-Under "forms" the same line reports, each against plain one-grid-at-a-time
-FP64 on the same GPU:
+Under "forms" the same line reports:
+  tol      the benchmark grid solved to max |du| < 1e-8 (checked every 10);
+  paper    the paper's own configuration (omega 0.376, north edge 1, other
+           edges 0, tol 1e-5 checked every 4000 iterations, at most 50000),
+           with the iteration count the paper does not print;
+and, each against plain one-grid-at-a-time FP64 on the same GPU:
   mixed    4096^2 Poisson (f = N(0,1) + 2 pi^2 sin sin, seed 3): FP64 defect
            correction around FP32 and binary16 inner sweeps vs plain FP64 SOR
            to the same relative residual, errors against the exact discrete
            solution (DST-I);
   batched  512 grids, sides log-uniform in [64, 1024] (seed 4), f = N(0,1) on
-           odd grids, omega_opt, tol 1e-8: one persistent launch, FP64 and
+           odd grids, omega_opt, tol 1e-8: one persistent launch, FP64 (with
+           the size rule's tiles and with autotuned tiles) and
            FP32+refinement, solves/s;
   serving  Poisson arrivals (seed 5) of requests with sides log-uniform in
            [128, 2048], boundary U[0,100], f = N(0,1), each to relative
@@ -229,7 +234,62 @@ def form_batched(sor, ctx, torch):
                                  "glups": round(its / dt / 1e9, 1)}
     out["speedup_batched_vs_one_at_a_time"] = round(
         out["fp64_batched"]["solves_per_s"] / out["fp64_one_at_a_time"]["solves_per_s"], 2)
+
+    # Autotuned tiles: one batched-throughput search per half-octave size
+    # class in the batch.
+    tuned = {}
+    for n in sorted({g.n for g in grids}):
+        c = round(2 * math.log2(n))
+        if c not in tuned:
+            tuned[c] = ctx.autotune_batch(64, n)
+    timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))           # re-records the graph
+    res, dt = timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))
+    out["fp64_batched_autotuned"] = {
+        "secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
+        "glups": round(sum(g.n * g.n * r.iterations for g, r in zip(grids, res)) / dt / 1e9, 1),
+        "converged": sum(r.converged for r in res),
+        "tilings": {str(k): list(v) for k, v in sorted(tuned.items())}}
+    ctx.set_tiling(64, 6, 0)       # back to the size rule for later forms
     return out
+
+
+def form_tol(sor, ctx, torch, n=4096, tol=1e-8, K=10, cap=100000):
+    """The benchmark grid solved to max |du| < tol (checked every K)."""
+    from workloads import laplace_random_boundary
+    g = laplace_random_boundary(n, seed=2)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve_f64(u, b, None, g.omega, tol, cap, K, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"laplace_random_boundary_{n} (seed 2), omega_opt, tol {tol}, "
+                        f"check every {K}",
+            "converged": bool(r.converged), "iterations": r.iterations,
+            "final_max_delta": r.final_max_delta, "secs": round(dt, 3),
+            "glups": round(n * n * r.iterations / dt / 1e9, 1)}
+
+
+def form_paper(sor, ctx, torch, n=4096):
+    """The paper's configuration: omega 0.376, north edge 1, other edges 0,
+    tol 1e-5 checked every 4000 iterations, at most 50000 (Sec. 2.1, Sec. 4).
+    Reports the iteration count at which the check passed, which the paper
+    does not print."""
+    from workloads import laplace_top_edge
+    g = laplace_top_edge(n, top=1.0, tol=1e-5, max_iters=50000, check_every=4000)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve_f64(u, b, None, 0.376, g.tol, g.max_iters, g.check_every, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"laplace_top_edge_{n}, north 1.0, omega 0.376, tol 1e-5, "
+                        "check every 4000, max 50000",
+            "converged": bool(r.converged), "iterations": r.iterations,
+            "final_max_delta": r.final_max_delta, "secs": round(dt, 3),
+            "glups": round(n * n * r.iterations / dt / 1e9, 1)}
 
 
 def percentile(xs, q):
@@ -321,9 +381,9 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="mixed,batched,serving",
+    ap.add_argument("--forms", default="tol,paper,mixed,batched,serving",
                     help="comma list of extra forms to measure, or 'none'")
-    ap.add_argument("--serve-requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-burst", type=int, default=80)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before timing, run one device-to-device copy of this "
@@ -416,6 +476,12 @@ def main():
     }
     forms = [] if args.forms == "none" else args.forms.split(",")
     line["forms"] = {}
+    if "tol" in forms:
+        print("[bench] form: 4096^2 to tolerance", file=sys.stderr, flush=True)
+        line["forms"]["tol"] = form_tol(sor, ctx, torch)
+    if "paper" in forms:
+        print("[bench] form: the paper's configuration", file=sys.stderr, flush=True)
+        line["forms"]["paper"] = form_paper(sor, ctx, torch)
     if "mixed" in forms:
         print("[bench] form: mixed precision 4096^2", file=sys.stderr, flush=True)
         line["forms"]["mixed"] = form_mixed(sor, ctx, torch)

@@ -112,7 +112,8 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * about as many tiles as the device holds resident wavefronts of the pass
  * kernel (4*2*iters_per_pass..768 rows); batched solves use 64 rows below
  * n = 512, else 192 (FP64) or 96.  An autotuned entry for the grid's size
- * class (sor_autotune) takes precedence over both. */
+ * class (sor_autotune for plain solves, sor_autotune_batch for batched ones)
+ * takes precedence. */
 typedef struct sor_tiling {
     int32_t iters_per_pass;
     int32_t seg_rows;
@@ -230,8 +231,8 @@ typedef struct sor_grid_desc {
  * graph and replayed for later batches with the same shapes.
  *   grids    HOST array of `count` descriptors (count >= 1)
  *   results  HOST array of `count` results (status per grid in ->status)
- * Tiles per grid come from the context's tuning table (sor_autotune) or a
- * size-based default.  Returns SOR_OK when every grid converged,
+ * Tiles per grid come from the context's batched tuning table
+ * (sor_autotune_batch) or a size-based default.  Returns SOR_OK when every grid converged,
  * SOR_NOT_CONVERGED when some reached their limit, SOR_ENONFINITE when some
  * produced a non-finite value, SOR_ETIMEOUT if a device-side queue wait
  * exceeded its bound, or an argument / device error.
@@ -240,15 +241,28 @@ sor_status sor_batch_solve_f64(sor_ctx *ctx, const sor_grid_desc *grids,
                                int32_t count, void *stream, sor_result *results);
 
 /*
- * Tiling autotuner: times blocked passes of every candidate tiling
- * (iterations per pass x rows per tile) on a scratch n x n grid of the given
- * storage precision (64 or 32 bits) with HIP events, stores the fastest in
- * the context's tuning table for n's size class (side rounded to the nearest
- * half power of two), and returns it in *best (may be NULL).  Later plain and
- * batched solves of that precision and class use it.  Only timing is
+ * Tiling autotuner for plain solves: times blocked passes of every candidate
+ * tiling (iterations per pass x rows per tile) on a scratch n x n grid of the
+ * given storage precision (64 or 32 bits) with HIP events, stores the fastest
+ * in the context's plain-solve tuning table for n's size class (side rounded
+ * to the nearest half power of two), and returns it in *best (may be NULL).
+ * Later plain solves of that precision and class use it.  Only timing is
  * measured: results never depend on the tiling.
  */
 sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best);
+
+/*
+ * Tiling autotuner for grids inside batched launches, where many grids share
+ * the chip and throughput, not one grid's pass latency, decides: solves a
+ * scratch batch of identical n x n grids (enough for about 4096 tiles, at
+ * most 256 grids and 1 GiB; 96 iterations each) once per candidate (1, 2 or
+ * 4 iterations per pass x 16..384 rows) with sor_batch_solve_f64 (bits 64)
+ * or the inner sweeps of sor_batch_solve_mixed (bits 32 or 16), keeps the
+ * fastest in the context's batched tuning table for n's size class (used by
+ * batched solves and by nothing else) and returns it in *best (may be NULL).
+ * n in 8..8192.  Results never depend on the tiling.
+ */
+sor_status sor_autotune_batch(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best);
 
 /*
  * One grid of a mixed-precision batched solve or of a served request: the

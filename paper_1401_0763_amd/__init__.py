@@ -132,6 +132,8 @@ def _declare(lib):
     lib.sor_batch_solve_f64.restype = ctypes.c_int
     lib.sor_autotune.argtypes = [P, i32, i32, ctypes.POINTER(_Tiling)]
     lib.sor_autotune.restype = ctypes.c_int
+    lib.sor_autotune_batch.argtypes = [P, i32, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_autotune_batch.restype = ctypes.c_int
     lib.sor_batch_solve_mixed.argtypes = [P, ctypes.POINTER(_MixedDesc), i32, i32, P,
                                           ctypes.POINTER(_Result)]
     lib.sor_batch_solve_mixed.restype = ctypes.c_int
@@ -226,6 +228,15 @@ class Context:
         seg_rows) and records it for n's size class."""
         t = _Tiling()
         self._check(self.lib.sor_autotune(self.handle, int(bits), int(n), ctypes.byref(t)))
+        return t.iters_per_pass, t.seg_rows
+
+    def autotune_batch(self, bits: int, n: int) -> tuple[int, int]:
+        """Time candidate tilings on a scratch batch of n x n grids; returns
+        (iters_per_pass, seg_rows) and records it for batched solves of n's
+        size class."""
+        t = _Tiling()
+        self._check(self.lib.sor_autotune_batch(self.handle, int(bits), int(n),
+                                                ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
 
     def get_tiling(self, bits: int) -> tuple[int, int]:

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -34,8 +35,10 @@ struct BatchState {
   long long wall_khz = 0;
   hipGraphExec_t exec = nullptr;
   std::vector<long long> sig;            // shapes the graph was recorded for
-  // size class -> tiling, per precision (autotuner results)
+  // size class -> tiling, per precision: autotuner results for plain solves
+  // (sor_autotune) and for grids inside batched launches (sor_autotune_batch)
   std::map<int, sor_tiling> tune[3];
+  std::map<int, sor_tiling> tune_batch[3];
 };
 
 void batch_state_free(sor_ctx *c) {
@@ -57,7 +60,7 @@ int size_class(int n) { return (int)std::lround(2.0 * std::log2((double)std::max
 
 sor_tiling batch_tiling(sor_ctx *c, int prec, int n) {
   if (c->batch) {
-    auto &m = c->batch->tune[prec];
+    auto &m = c->batch->tune_batch[prec];
     auto it = m.find(size_class(n));
     if (it != m.end()) return it->second;
   }
@@ -106,7 +109,10 @@ sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {
 }
 
 void clear_tuning(sor_ctx *c, int prec) {
-  if (c->batch) c->batch->tune[prec].clear();
+  if (c->batch) {
+    c->batch->tune[prec].clear();
+    c->batch->tune_batch[prec].clear();
+  }
 }
 
 namespace {
@@ -391,6 +397,79 @@ sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(c, SOR_EDEVICE, "autotune: %s", hipGetErrorString(e));
   bs->tune[prec][size_class(n)] = bt;
+  if (best) *best = bt;
+  return SOR_OK;
+}
+
+sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  const int prec = prec_index(bits);
+  if (prec < 0) return fail(c, SOR_EINVAL, "bits must be 64, 32 or 16");
+  if (n < 8 || n > 8192) return fail(c, SOR_EINVAL, "n = %d outside 8..8192", n);
+  HIP_TRY(c, hipSetDevice(c->device));
+  BatchState *bs = nullptr;
+  sor_status st = batch_state(c, &bs);
+  if (st != SOR_OK) return st;
+  // A batch of G identical grids, enough for about 4096 tiles at 4
+  // iterations per pass and 64-row tiles, capped at 256 grids and 1 GiB.
+  const BlockGeom g4 = block_geom(prec, 4);
+  const long long tiles = (long long)((n + 1 + g4.CW - 1) / g4.CW) * ((n + 1 + 63) / 64);
+  long long G = std::max(1LL, std::min(256LL, (4096 + tiles - 1) / tiles));
+  G = std::max(1LL, std::min(G, (long long)((1ull << 30) / ((size_t)n * n * 8 * 3))));
+  const size_t cells = (size_t)n * n;
+  double *u = nullptr, *bdy = nullptr;
+  if (hipMalloc(&u, sizeof(double) * cells * G) != hipSuccess ||
+      hipMalloc(&bdy, sizeof(double) * 4 * n) != hipSuccess) {
+    (void)hipGetLastError();
+    if (u) (void)hipFree(u);
+    return fail(c, SOR_ENOMEM, "autotune_batch: cannot allocate %lld grids of side %d", G, n);
+  }
+  std::vector<double> hb(4 * (size_t)n, 1.0);
+  hipError_t he = hipMemcpy(bdy, hb.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
+  const double omega = 2.0 / (1.0 + std::sin(M_PI / (n + 1)));
+  const int iters = 96;                                 // divisible by 1, 2, 4
+  std::vector<sor_grid_desc> gd((size_t)G);
+  std::vector<sor_mixed_desc> md((size_t)G);
+  for (long long g = 0; g < G; ++g) {
+    gd[g] = sor_grid_desc{u + cells * g, bdy, nullptr, n, 0, omega, 0.0, iters, iters};
+    md[g] = sor_mixed_desc{u + cells * g, bdy, nullptr, n, 0, omega, 0.0, 0.0, 1, iters};
+  }
+  std::vector<sor_result> res((size_t)G);
+  auto &table = bs->tune_batch[prec];
+  const int cls = size_class(n);
+  const auto saved = table.find(cls) != table.end() ? table[cls] : sor_tiling{0, 0};
+  sor_tiling bt{4, 64};
+  double best_t = INFINITY;
+  for (int T : {1, 2, 4}) {
+    for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384}) {
+      if (he != hipSuccess) break;
+      if (seg > 2 * (n + 1) && seg != 16) continue;
+      table[cls] = sor_tiling{T, seg};
+      double tmin = INFINITY;
+      for (int rep = 0; rep < 3; ++rep) {              // first run records the graph
+        if (hipMemset(u, 0, sizeof(double) * cells * G) != hipSuccess) { he = hipErrorUnknown; break; }
+        const auto t0 = std::chrono::steady_clock::now();
+        const sor_status s2 =
+            prec == kF64 ? sor_batch_solve_f64(c, gd.data(), (int32_t)G, nullptr, res.data())
+                         : sor_batch_solve_mixed(c, md.data(), (int32_t)G, bits, nullptr, res.data());
+        const auto t1 = std::chrono::steady_clock::now();
+        if (s2 < 0) { he = hipErrorUnknown; break; }
+        if (rep > 0) tmin = std::min(tmin, std::chrono::duration<double>(t1 - t0).count());
+      }
+      if (tmin < best_t) {
+        best_t = tmin;
+        bt = sor_tiling{T, seg};
+      }
+    }
+  }
+  (void)hipFree(u);
+  (void)hipFree(bdy);
+  if (he != hipSuccess) {
+    if (saved.iters_per_pass) table[cls] = saved; else table.erase(cls);
+    return fail(c, SOR_EDEVICE, "autotune_batch: %s", c->err.empty() ? "device error" : c->err.c_str());
+  }
+  table[cls] = bt;
   if (best) *best = bt;
   return SOR_OK;
 }

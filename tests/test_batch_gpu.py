@@ -131,3 +131,23 @@ def test_autotune_returns_supported_tiling_and_keeps_results(sor, ctx):
     u = dev(g.u0)
     sor.solve_f64(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 30, 1, ctx=ctx)
     assert bitwise(u.cpu().numpy(), ref.u)
+
+
+def test_batch_autotune_returns_supported_tiling_and_keeps_results(sor, ctx):
+    """The batched tuner records a tiling for the class of n = 100 only in the
+    batched table; batches of that class still equal the oracle bit for bit,
+    and a plain solve keeps its own tiling."""
+    plain_before = ctx.tiling_for(64, 100)
+    T, seg = ctx.autotune_batch(64, 100)
+    assert T in (1, 2, 4) and 16 <= seg <= 384
+    assert ctx.tiling_for(64, 100) == plain_before
+    grids = []
+    for k in range(4):
+        g = random_small(300 + k, 100, with_f=bool(k % 2))
+        g.tol, g.max_iters, g.check_every = 1e-7, 3000, 1
+        grids.append(g)
+    res, us = run_batch(sor, ctx, grids)
+    for g, r, u in zip(grids, res, us):
+        ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, g.tol, g.max_iters, 1)
+        assert r.iterations == ref.iterations and r.status == ref.status
+        assert bitwise(u, ref.u)
