@@ -91,10 +91,14 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
   for (int k = 1; k <= 64; ++k) {
     const long long segs = std::max(1LL, k * slots / strips);
     seg = (int)((n + 1 + segs - 1) / segs);
-    seg += seg & 1;
     if (seg <= hi) break;
   }
-  return std::min(hi, std::max(lo, seg));
+  seg = std::min(hi, std::max(lo, seg));
+  // A tile walks seg + 2S - 2 steps in chunks of W: round seg up so that the
+  // last chunk is full (fewer tiles, none of their steps wasted).
+  const int over = (seg + 2 * gm.S - 2) % gm.W;
+  if (over) seg += gm.W - over;
+  return std::min(1024, seg + (seg & 1));
 }
 
 sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {

@@ -257,6 +257,7 @@ BlockGeom block_geom(int prec, int T) {
   g.S = 2 * T;
   g.A = ((g.S + g.V - 1) / g.V) * g.V;
   g.CW = kLanes * g.V - 2 * g.A;
+  g.W = blocked_window_rows(T);
   return g;
 }
 

@@ -233,6 +233,7 @@ int batch_waves_per_cu_f64();
 // Geometry of the blocked kernel for a precision and iterations-per-pass T.
 struct BlockGeom {
   int V, S, A, CW;
+  int W;        // steps per chunk of the row walk (window rows)
 };
 BlockGeom block_geom(int prec, int T);
 

@@ -214,6 +214,13 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
   }
 }
 
+// Rows of the register window of a T-deep tile: the 2T stage rows, their
+// neighbours and the SOR_PREFETCH rows loaded ahead, rounded up to even.  The
+// row walk runs in chunks of this many steps.
+__host__ __device__ constexpr int blocked_window_rows(int T) {
+  return ((2 * T + SOR_PREFETCH + 2) + 1) / 2 * 2;
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked streaming sweep of one tile by one wavefront.
 //
@@ -267,7 +274,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   constexpr int WV = kLanes * V;
   constexpr int CW = WV - 2 * A;
   constexpr int D = SOR_PREFETCH;                // rows prefetched ahead
-  constexpr int W = ((S + D + 2) + 1) / 2 * 2;   // window rows (even)
+  constexpr int W = blocked_window_rows(T);      // window rows (even)
   constexpr int ESZ = (int)sizeof(st);
 
   const int lane = threadIdx.x & 63;
