@@ -8,7 +8,8 @@ this module only marshals numpy arrays to it.
 
 Functions follow Mittal (2014): Sec. 2.1 Eq. 1 (the SOR update), Sec. 3.1 and
 Fig. 1-2 (red-black colouring, red phase first), Algorithm 1 (iteration,
-check every K iterations, strict ``max change < eps`` stopping rule).
+check every K iterations, strict ``max change < eps`` stopping rule); the 3-D
+7-point form is the extension named in Sec. 5.
 """
 from __future__ import annotations
 
@@ -64,6 +65,10 @@ def _load():
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                  ctypes.c_int, ctypes.c_int64, i64p, dp, dp, dp]
     lib.oracle_mixed.restype = ctypes.c_int
+    lib.oracle_sor3d_f64.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_int64,
+                                     ctypes.c_int64, ctypes.c_int, i64p, dp, dp]
+    lib.oracle_sor3d_f64.restype = ctypes.c_int
     lib.oracle_round_half.argtypes = [ctypes.c_float]
     lib.oracle_round_half.restype = ctypes.c_float
     _lib = lib
@@ -195,6 +200,34 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
         raise ValueError(f"oracle_mixed rejected its arguments (status {st})")
     return MixedResult(u, st, outer.value, rel.value, rh[: outer.value + 1],
                        corr.value)
+
+
+def sor3d_f64(u0, bdy, f, omega, tol, max_iters, check_every=1, threads=1,
+              hist=False) -> SorResult:
+    """FP64 red-black SOR on the 7-point stencil of the unit cube: u0 is
+    (n, n, n) indexed [z][y][x], bdy (6, n, n) holds the faces x = 0, x = n+1
+    ([z][y]), y = 0, y = n+1 ([z][x]), z = 0, z = n+1 ([y][x])."""
+    lib = _load()
+    b = np.ascontiguousarray(np.asarray(bdy, dtype=np.float64).reshape(-1))
+    n = int(round((b.size // 6) ** 0.5))
+    if 6 * n * n != b.size:
+        raise ValueError("bdy must hold 6 faces of n*n values")
+    u = np.ascontiguousarray(np.array(u0, dtype=np.float64).reshape(n, n, n))
+    ff = None if f is None else np.ascontiguousarray(
+        np.asarray(f, dtype=np.float64).reshape(n, n, n))
+    it = ctypes.c_int64(0)
+    mx = ctypes.c_double(0.0)
+    mh = np.zeros(max_iters, dtype=np.float64) if hist else None
+    st = lib.oracle_sor3d_f64(n, _ptr(u, ctypes.c_double), _ptr(b, ctypes.c_double),
+                              _ptr(ff, ctypes.c_double), float(omega), float(tol),
+                              int(max_iters), int(check_every), int(threads),
+                              ctypes.byref(it), ctypes.byref(mx),
+                              _ptr(mh, ctypes.c_double))
+    if st < 0 and st != ENONFINITE:
+        raise ValueError(f"oracle_sor3d_f64 rejected its arguments (status {st})")
+    if mh is not None:
+        mh = mh[: it.value]
+    return SorResult(u, st, it.value, mx.value, mh)
 
 
 def round_half(x: float) -> float:

@@ -3,7 +3,8 @@
  * over-relaxation (SOR) on the 5-point discretisation of the 2-D steady-state
  * heat conduction problem with Dirichlet boundaries (Mittal, "A Study of
  * Successive Over-relaxation Method Parallelization Over Modern HPC
- * Languages", 2014).
+ * Languages", 2014), and on the 7-point discretisation of its 3-D form (the
+ * extension the paper names as future work, Sec. 5; last section below).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
  * benchmark's CPU-baseline leg may load or call this file.  It shares no code,
@@ -490,5 +491,149 @@ int oracle_mixed(int n, double *u, const double *bdy, const double *f,
     if (rel_out) *rel_out = rel;
     if (corr_out) *corr_out = last_corr;
     free(U); free(r); free(E); free(R); free(F);
+    return status;
+}
+
+/* ======================================================================== */
+/* 3-D red-black SOR, 7-point stencil (the paper's stated extension, Sec. 5) */
+/* ======================================================================== */
+/*
+ * Grid convention in 3-D: the n x n x n interior of the unit cube is embedded
+ * in an (n+2)^3 array V indexed V[z][y][x] (x fastest), with the Dirichlet
+ * boundary on the six faces.  Cell (z, y, x), indices into the full array,
+ * is red when z + y + x is even (the 2-D rule of Sec. 3.1 with one more
+ * axis), so interior cell (1, 1, 1) is black and (1, 1, 2) red; red cells are
+ * updated first.
+ *
+ * User-facing arrays:
+ *   u    n^3 interior values, u[((z-1)*n + (y-1))*n + (x-1)] is V[z][y][x].
+ *   bdy  6 faces of n*n values in the order x = 0, x = n+1 (indexed [z][y]),
+ *        y = 0, y = n+1 (indexed [z][x]), z = 0, z = n+1 (indexed [y][x]),
+ *        each row-major over its two indices 1..n.
+ *   f    n^3 source of -lap(u) = f, laid out like u, or NULL.
+ *
+ * The Gauss-Seidel value of a cell is the average of its six neighbours: the
+ * sum is formed as ((W + E) + (N + S)) + (D + U) with W/E the x-, N/S the y-
+ * and D/U the z-neighbours, then + F with F = h*h*f, then multiplied by
+ * SIXTH = fl(1/6) (one rounding; 1/6 is not a power of two, so this product
+ * is fixed here as the definition two implementations share).  The update,
+ * change and stopping rule are those of the 2-D oracle (Eq. 1 in increment
+ * form, Algorithm 1).
+ */
+#define AT3(z, y, x) (((size_t)(z) * (size_t)(n + 2) + (size_t)(y)) * (size_t)(n + 2) + (size_t)(x))
+
+static const double ORC_SIXTH = 1.0 / 6.0;
+
+static void orc_fill3_f64(int n, double *V, const double *u, const double *bdy)
+{
+    size_t nn = (size_t)n * (size_t)n;
+    memset(V, 0, sizeof(double) * (size_t)(n + 2) * (size_t)(n + 2) * (size_t)(n + 2));
+    for (int z = 1; z <= n; ++z)
+        for (int y = 1; y <= n; ++y)
+            for (int x = 1; x <= n; ++x)
+                V[AT3(z, y, x)] = u[((size_t)(z - 1) * n + (y - 1)) * n + (x - 1)];
+    for (int a = 1; a <= n; ++a)
+        for (int c = 1; c <= n; ++c) {
+            size_t k = (size_t)(a - 1) * n + (c - 1);
+            V[AT3(a, c, 0)] = bdy[0 * nn + k];          /* x = 0,   [z][y] */
+            V[AT3(a, c, n + 1)] = bdy[1 * nn + k];      /* x = n+1, [z][y] */
+            V[AT3(a, 0, c)] = bdy[2 * nn + k];          /* y = 0,   [z][x] */
+            V[AT3(a, n + 1, c)] = bdy[3 * nn + k];      /* y = n+1, [z][x] */
+            V[AT3(0, a, c)] = bdy[4 * nn + k];          /* z = 0,   [y][x] */
+            V[AT3(n + 1, a, c)] = bdy[5 * nn + k];      /* z = n+1, [y][x] */
+        }
+}
+
+/* One half-sweep of one colour over planes z_lo..z_hi, in place. */
+static double orc_half_sweep3_f64(int n, double *V, const double *F, double w,
+                                  int colour, int z_lo, int z_hi, int *bad)
+{
+    double m = 0.0;
+    for (int z = z_lo; z <= z_hi; ++z)
+        for (int y = 1; y <= n; ++y) {
+            int x0 = 1 + ((z + y + 1 + colour) & 1);   /* first x with the colour */
+            for (int x = x0; x <= n; x += 2) {
+                double old = V[AT3(z, y, x)];
+                double s = ((V[AT3(z, y, x - 1)] + V[AT3(z, y, x + 1)]) +
+                            (V[AT3(z, y - 1, x)] + V[AT3(z, y + 1, x)])) +
+                           (V[AT3(z - 1, y, x)] + V[AT3(z + 1, y, x)]);
+                if (F) s = s + F[AT3(z, y, x)];
+                double gs = ORC_SIXTH * s;
+                double nu = old + w * (gs - old);
+                double d = fabs(nu - old);
+                if (!isfinite(nu)) *bad = 1;
+                if (d > m) m = d;
+                V[AT3(z, y, x)] = nu;
+            }
+        }
+    return m;
+}
+
+/*
+ * 3-D red-black SOR with Algorithm 1's control (same arguments and outputs as
+ * oracle_sor_f64; threads > 1 splits the planes of each colour across OpenMP
+ * workers, bitwise identical to one thread).
+ */
+int oracle_sor3d_f64(int n, double *u, const double *bdy, const double *f,
+                     double omega, double tol, int64_t max_iters,
+                     int64_t check_every, int threads, int64_t *iters_out,
+                     double *max_out, double *mhist)
+{
+    if (n < 1 || !u || !bdy || !(omega > 0.0 && omega < 2.0) || !(tol >= 0.0) ||
+        max_iters < 1 || check_every < 1 || threads < 1)
+        return ORC_EINVAL;
+    size_t cells = (size_t)(n + 2) * (size_t)(n + 2) * (size_t)(n + 2);
+    double *V = malloc(sizeof(double) * cells);
+    if (!V) return ORC_ENOMEM;
+    double *F = NULL;
+    if (f) {
+        F = calloc(cells, sizeof(double));
+        if (!F) { free(V); return ORC_ENOMEM; }
+        double h = orc_h(n);
+        double h2 = h * h;
+        for (int z = 1; z <= n; ++z)
+            for (int y = 1; y <= n; ++y)
+                for (int x = 1; x <= n; ++x)
+                    F[AT3(z, y, x)] = h2 * f[((size_t)(z - 1) * n + (y - 1)) * n + (x - 1)];
+    }
+    orc_fill3_f64(n, V, u, bdy);
+    int status = ORC_NOT_CONVERGED;
+    int64_t it = 0;
+    double last = NAN;
+    for (it = 1; it <= max_iters; ++it) {
+        double m = 0.0;
+        int bad = 0;
+        for (int colour = 0; colour < 2; ++colour) {
+            double mc = 0.0;
+            int badc = 0;
+            if (threads == 1) {
+                mc = orc_half_sweep3_f64(n, V, F, omega, colour, 1, n, &badc);
+            } else {
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(max : mc) reduction(| : badc)
+                for (int z = 1; z <= n; ++z) {
+                    int b1 = 0;
+                    double r = orc_half_sweep3_f64(n, V, F, omega, colour, z, z, &b1);
+                    if (r > mc) mc = r;
+                    badc |= b1;
+                }
+            }
+            if (mc > m) m = mc;
+            bad |= badc;
+        }
+        if (mhist) mhist[it - 1] = m;
+        if (bad) { status = ORC_ENONFINITE; last = m; break; }
+        if (it % check_every == 0 || it == max_iters) {
+            last = m;
+            if (m < tol) { status = ORC_OK; break; }
+        }
+    }
+    if (it > max_iters) it = max_iters;
+    for (int z = 1; z <= n; ++z)
+        for (int y = 1; y <= n; ++y)
+            for (int x = 1; x <= n; ++x)
+                u[((size_t)(z - 1) * n + (y - 1)) * n + (x - 1)] = V[AT3(z, y, x)];
+    if (iters_out) *iters_out = it;
+    if (max_out) *max_out = last;
+    free(V); free(F);
     return status;
 }
