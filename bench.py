@@ -295,6 +295,35 @@ def form_paper(sor, ctx, torch, n=4096):
             "glups": round(n * n * r.iterations / dt / 1e9, 1)}
 
 
+def form_3d(sor, ctx, torch, n=256, iters=1000):
+    """The 3-D extension (7-point stencil on the unit cube): 256^3 interior
+    cells, random boundary faces, omega_opt; a fixed iteration count for the
+    update rate, then a solve to 1e-8 checked every 10 iterations."""
+    from workloads import random_cube
+    g = random_cube(21, n, with_f=False)
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    u = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    sor.solve3d_f64(u, b, None, g.omega, 0.0, 20, 10, ctx=ctx)       # warm-up
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve3d_f64(u, b, None, g.omega, 0.0, iters, 10, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": f"laplace_random_faces_{n}^3, omega_opt",
+           "iterations": r.iterations, "secs": round(dt, 3),
+           "glups": round(n ** 3 * r.iterations / dt / 1e9, 2),
+           "hbm_equiv_GBs": round(16.0 * n ** 3 * r.iterations / dt / 1e9, 1)}
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve3d_f64(u, b, None, g.omega, 1e-8, 100000, 10, ctx=ctx)
+    torch.cuda.synchronize()
+    out["tol_1e-8"] = {"converged": bool(r.converged), "iterations": r.iterations,
+                       "secs": round(time.perf_counter() - t0, 3)}
+    return out
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -384,7 +413,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="tol,paper,mixed,batched,serving",
+    ap.add_argument("--forms", default="tol,paper,mixed,batched,3d,serving",
                     help="comma list of extra forms to measure, or 'none'")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-burst", type=int, default=80)
@@ -491,6 +520,9 @@ def main():
     if "batched" in forms:
         print("[bench] form: batched 512 grids", file=sys.stderr, flush=True)
         line["forms"]["batched"] = form_batched(sor, ctx, torch)
+    if "3d" in forms:
+        print("[bench] form: 3-D 256^3", file=sys.stderr, flush=True)
+        line["forms"]["3d"] = form_3d(sor, ctx, torch)
     if "serving" in forms:
         print("[bench] form: serving", file=sys.stderr, flush=True)
         line["forms"]["serving"] = form_serving(sor, ctx, torch, args.serve_requests,

@@ -166,6 +166,29 @@ sor_status sor_solve_f32(sor_ctx *ctx, float *u, const float *boundary,
                          sor_result *out, double *max_hist);
 
 /*
+ * FP64 red-black SOR on the 7-point discretisation of the 3-D problem on the
+ * unit cube, the extension named as future work in Sec. 5: the same update
+ * (Sec. 2.1 Eq. 1 in increment form), colouring (Sec. 3.1 with a third axis:
+ * cell (z, y, x) of the (n+2)^3 array is red when z + y + x is even, red
+ * first) and stopping rule (Algorithm 1) as sor_solve_f64.  The Gauss-Seidel
+ * value is (((W + E) + (N + S)) + (D + U) [+ h*h*f]) * fl(1/6), W/E, N/S and
+ * D/U the x-, y- and z-neighbours, no fused multiply-add.
+ *   u         DEVICE n*n*n, index ((z-1)*n + (y-1))*n + (x-1): in initial
+ *             guess, out result (caller-owned)
+ *   boundary  DEVICE 6*n*n: faces x = 0 and x = n+1 (each indexed
+ *             (z-1)*n + (y-1)), y = 0 and y = n+1 ((z-1)*n + (x-1)),
+ *             z = 0 and z = n+1 ((y-1)*n + (x-1)), in that order
+ *   rhs       DEVICE n*n*n source of -lap(u) = f like u, or NULL
+ *   n in 1..1024; other arguments, results and errors as for sor_solve_f64
+ *   (out->passes counts iterations; max_hist, if not NULL, HOST max_iters
+ *   doubles).  One kernel launch per colour and iteration.
+ */
+sor_status sor_solve3d_f64(sor_ctx *ctx, double *u, const double *boundary,
+                           const double *rhs, int32_t n, double omega, double tol,
+                           int64_t max_iters, int64_t check_every, void *stream,
+                           sor_result *out, double *max_hist);
+
+/*
  * FP64 residual of the h*h-scaled system 4u - (interior neighbours) = b,
  * b = h*h*f + (boundary neighbours):
  *   r = (h*h*f + ((N + S) + (W + E))) - 4u   at every interior cell.

@@ -119,7 +119,7 @@ def _declare(lib):
     lib.sor_ctx_tiling_for.restype = ctypes.c_int
     solve_args = [P, P, P, P, i32, dbl, dbl, i64, i64, P,
                   ctypes.POINTER(_Result), P]
-    for name in ("sor_solve_f64", "sor_solve_f32"):
+    for name in ("sor_solve_f64", "sor_solve_f32", "sor_solve3d_f64"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = ctypes.c_int
     lib.sor_residual_f64.argtypes = [P, P, P, P, i32, P, P, P]
@@ -372,6 +372,30 @@ def solve_f32(u, boundary, rhs=None, omega=None, tol=1e-5, max_iters=100000,
     ctx = ctx or context(u.device.index)
     return _solve_plain(ctx.lib.sor_solve_f32, torch.float32, u, boundary, rhs,
                         omega, tol, max_iters, check_every, hist, ctx)
+
+
+def solve3d_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
+                check_every=1, hist=False, ctx: Context | None = None) -> Result:
+    """FP64 red-black SOR on the 7-point stencil of the unit cube, in place on
+    u (n x n x n float64 CUDA tensor indexed [z][y][x]); boundary (6, n, n)
+    holds the faces x = 0, x = n+1 ([z][y]), y = 0, y = n+1 ([z][x]),
+    z = 0, z = n+1 ([y][x]); rhs (n, n, n) or None."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    pu = _check_tensor("u", u, torch.float64, (n, n, n))
+    pb = _check_tensor("boundary", boundary, torch.float64, (6, n, n))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n, n))
+    ctx = ctx or context(u.device.index)
+    res = _Result()
+    hbuf = (ctypes.c_double * int(max_iters))() if hist else None
+    st = ctx.lib.sor_solve3d_f64(ctx.handle, pu, pb, pf, int(n), float(omega), float(tol),
+                                 int(max_iters), int(check_every), _stream_handle(u),
+                                 ctypes.byref(res), hbuf)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    h = list(hbuf[: res.iterations]) if hist else None
+    return _result(st, res, h)
 
 
 def residual_f64(u, boundary, rhs=None, r=None, ctx: Context | None = None):

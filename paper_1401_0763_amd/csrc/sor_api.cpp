@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "sor_host.h"
+#include "sor_3d.h"
 
 using namespace sor;
 
@@ -263,6 +264,68 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   }
 }
 
+// 3-D solve: iterations (red + black launch each) in chunks of 1, 2, 4 ...
+// 64, the device verdict read back after each chunk (the 2-D loop with
+// one-iteration passes and no re-run, since a pass never overshoots).
+sor_status run_iterations3d(sor_ctx *c, double *U, const double *F, int n, double omega,
+                            const Sched &sc, hipStream_t s, sor_result *res,
+                            double *hist) {
+  Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
+  HIP_TRY(c, launch_ctl_reset(ctl, s));
+  long long done = 0, chunk = 1;
+  res->converged = 0;
+  res->iterations = sc.max_iters;
+  res->final_max_delta = NAN;
+  for (;;) {
+    const long long chunk_it0 = done;
+    long long k = 0;
+    for (; k < chunk && done < sc.max_iters; ++k) {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (c->prof) {
+        sor_status pst = prof_events(c, (size_t)k, &e0, &e1);
+        if (pst != SOR_OK) return pst;
+        HIP_TRY(c, hipEventRecord(e0, s));
+      }
+      HIP_TRY(c, launch_sor3d_iteration(U, F, n, omega, ctl, sc, s));
+      if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
+      done += 1;
+      if (done - chunk_it0 >= kHistCap - 1) { ++k; break; }
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    const Ctl &h = *c->host_ctl;
+    const long long hist_end = h.stop ? h.stop_iter : done;
+    if (c->prof) {
+      for (long long j = 0; j < k; ++j) {
+        if (h.stop && chunk_it0 + j >= h.stop_iter) break;    // exited early
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]));
+        c->prof_ms += ms;
+        c->prof_launches += 1;
+      }
+    }
+    if (hist)
+      for (long long it = chunk_it0 + 1; it <= std::min(hist_end, sc.max_iters); ++it)
+        hist[it - 1] = h.hist[(it - 1) % kHistCap];
+    if (h.stop) {
+      res->iterations = h.stop_iter;
+      res->final_max_delta = h.stop_max;
+      res->passes = h.passes_done;
+      if (h.stop == 2)
+        return fail(c, SOR_ENONFINITE, "non-finite value in the grid by iteration %lld",
+                    h.stop_iter);
+      res->converged = 1;
+      return SOR_OK;
+    }
+    if (done >= sc.max_iters) {
+      res->final_max_delta = h.last_max;
+      res->passes = h.passes_done;
+      return SOR_NOT_CONVERGED;
+    }
+    chunk = std::min<long long>(chunk * 2, 64);
+  }
+}
+
 sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K) {
   if (!(tol >= 0.0)) return fail(c, SOR_EINVAL, "tol = %g must be >= 0", tol);
   if (max_iters < 1) return fail(c, SOR_EINVAL, "max_iters must be >= 1");
@@ -427,6 +490,36 @@ sor_status sor_solve_f32(sor_ctx *c, float *u, const float *bdy, const float *rh
                          double *max_hist) {
   return solve_plain<float>(c, kF32, u, bdy, rhs, n, omega, tol, max_iters,
                             check_every, stream, out, max_hist);
+}
+
+sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const double *rhs,
+                           int32_t n, double omega, double tol, int64_t max_iters,
+                           int64_t check_every, void *stream, sor_result *out,
+                           double *hist) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (n < 1 || n > kMaxN3) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN3);
+  sor_status st = check_common(c, u, bdy, rhs, n, omega);
+  if (st != SOR_OK) return st;
+  if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
+  if ((st = check_sched(c, tol, max_iters, check_every)) != SOR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t elems = (size_t)grid3_pitch(n) * (size_t)(n + 2) * (size_t)(n + 2);
+  if ((st = ensure(c, kGridA64, elems * sizeof(double)))) return st;
+  if (rhs && (st = ensure(c, kF64Buf, elems * sizeof(double)))) return st;
+  double *U = (double *)c->bufs[kGridA64].p;
+  double *F = rhs ? (double *)c->bufs[kF64Buf].p : nullptr;
+  unsigned *bad = &((Ctl *)c->bufs[kCtlBuf].p)->input_nonfinite;
+  HIP_TRY(c, launch_pack3d(u, bdy, rhs, U, F, n, bad, s));
+  *out = sor_result{};
+  out->rel_residual = NAN;
+  const Sched sc{max_iters, check_every, tol};
+  st = run_iterations3d(c, U, F, n, omega, sc, s, out, hist);
+  if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
+    HIP_TRY(c, launch_unpack3d(U, u, n, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return st;
 }
 
 sor_status sor_residual_f64(sor_ctx *c, const double *u, const double *bdy,

@@ -1,0 +1,141 @@
+"""GPU parity of the 3-D path (7-point red-black SOR on the unit cube, the
+extension Sec. 5 of Mittal 2014 names as future work) against the 3-D oracle
+on identical seeded inputs: the final grid and every iteration's largest
+change agree bit for bit (same update expression and sum order, no
+contraction, exact maxima), and a solve to tolerance stops at the same
+checked iteration."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import omega_opt, random_cube
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sor():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm device")
+    import paper_1401_0763_amd as m
+    return m
+
+
+@pytest.fixture()
+def ctx(sor):
+    c = sor.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return None if a is None else torch.tensor(np.ascontiguousarray(a), dtype=torch.float64,
+                                               device="cuda")
+
+
+def assert_bitwise(a, b, what):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    if not np.array_equal(a.view(np.uint64), b.view(np.uint64)):
+        diff = np.abs(a - b)
+        k = np.unravel_index(np.argmax(diff), diff.shape)
+        raise AssertionError(f"{what}: {np.count_nonzero(diff)} differ; max {diff.max()} at {k}")
+
+
+def run3(sor, ctx, g, tol, iters, K, hist=True):
+    u = dev(g.u0)
+    res = sor.solve3d_f64(u, dev(g.bdy), dev(g.f), g.omega, tol, iters, K, hist=hist, ctx=ctx)
+    return res, u.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,with_f,iters", [
+    (1, True, 5), (2, False, 7), (3, True, 9), (5, True, 11), (16, False, 13),
+    (33, True, 17), (64, True, 6), (67, False, 9), (130, True, 4)])
+def test_fixed_iterations_bitwise(sor, ctx, n, with_f, iters):
+    g = random_cube(300 + n, n, with_f=with_f, nonzero_u0=True)
+    _say(f"3d n={n} f={with_f} iters={iters}")
+    ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, g.omega, 0.0, iters, 1, threads=8, hist=True)
+    res, u = run3(sor, ctx, g, 0.0, iters, 1)
+    assert res.status == sor.NOT_CONVERGED and res.iterations == iters
+    assert_bitwise(u, ref.u, f"u n={n}")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n}")
+
+
+@pytest.mark.parametrize("omega", [0.376, 1.0, 1.5, 1.95])
+def test_omega_values_bitwise(sor, ctx, omega):
+    g = random_cube(77, 21, with_f=True, omega=omega)
+    _say(f"3d omega={omega}")
+    ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, omega, 0.0, 25, 1, threads=8, hist=True)
+    res, u = run3(sor, ctx, g, 0.0, 25, 1)
+    assert_bitwise(u, ref.u, f"u omega={omega}")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"hist omega={omega}")
+
+
+@pytest.mark.parametrize("K", [1, 5, 10])
+def test_to_tolerance_same_stop(sor, ctx, K):
+    """Converges; stops at the same checked iteration with the same change
+    and the same grid (the chunked host loop never overshoots the stop)."""
+    n = 24
+    g = random_cube(11, n, with_f=False)
+    for tol in (1e-3, 1e-8):
+        _say(f"3d tol={tol} K={K}")
+        ref = oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, tol, 100000, K, threads=8, hist=True)
+        assert ref.status == oracle.OK
+        res, u = run3(sor, ctx, g, tol, 100000, K)
+        assert res.status == sor.OK and res.converged
+        assert res.iterations == ref.iterations and res.iterations % K == 0
+        assert res.final_max_delta == ref.final_max_delta
+        assert_bitwise(u, ref.u, "u")
+        assert_bitwise(np.array(res.hist), ref.mhist, "hist")
+
+
+def test_poisson_to_tolerance_and_max_iters_check(sor, ctx):
+    """A solve that ends at max_iters (not a multiple of K) checks there."""
+    n = 31
+    g = random_cube(12, n, with_f=True)
+    ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, g.omega, 1e-12, 173, 10, threads=8)
+    res, u = run3(sor, ctx, g, 1e-12, 173, 10, hist=False)
+    assert res.status == sor.NOT_CONVERGED and ref.status == oracle.NOT_CONVERGED
+    assert res.iterations == 173 and res.final_max_delta == ref.final_max_delta
+    assert_bitwise(u, ref.u, "u")
+
+
+def test_sampled_cells_at_256_against_converged_oracle(sor, ctx):
+    """n = 256 at the bench's configuration: run the same fixed iteration count
+    on both sides and compare the full grid (the oracle at 8 threads)."""
+    n = 256
+    g = random_cube(9, n, with_f=False)
+    iters = 20
+    _say("3d n=256 oracle")
+    ref = oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, 0.0, iters, 1, threads=8, hist=True)
+    _say("3d n=256 gpu")
+    res, u = run3(sor, ctx, g, 0.0, iters, 1)
+    assert_bitwise(u, ref.u, "u n=256")
+    assert_bitwise(np.array(res.hist), ref.mhist, "hist n=256")
+
+
+def test_nonfinite_input_and_invalid_arguments(sor, ctx):
+    n = 9
+    g = random_cube(5, n, with_f=True)
+    bdy = g.bdy.copy()
+    bdy[3, 4, 4] = np.inf
+    ref = oracle.sor3d_f64(g.u0, bdy, g.f, g.omega, 1e-8, 50, 1)
+    assert ref.status == oracle.ENONFINITE
+    res = sor.solve3d_f64(dev(g.u0), dev(bdy), dev(g.f), g.omega, 1e-8, 50, 1, ctx=ctx)
+    assert res.status == sor.ENONFINITE and not res.converged
+    with pytest.raises(sor.SorError):
+        sor.solve3d_f64(dev(g.u0), dev(g.bdy), None, 2.0, 1e-8, 10, 1, ctx=ctx)
+    with pytest.raises(sor.SorError):
+        sor.solve3d_f64(dev(g.u0), dev(g.bdy), None, 1.5, 1e-8, 0, 1, ctx=ctx)
+    # the context stays usable after the errors
+    ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, g.omega, 0.0, 8, 1, hist=True)
+    res, u = run3(sor, ctx, g, 0.0, 8, 1)
+    assert_bitwise(u, ref.u, "u after errors")

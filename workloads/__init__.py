@@ -107,6 +107,18 @@ def random_small(seed: int, n: int, with_f: bool = True, omega: float | None = N
     return Grid(n, u0, bdy, f, omega_opt(n) if omega is None else omega)
 
 
+def random_cube(seed: int, n: int, with_f: bool = True, omega: float | None = None,
+                nonzero_u0: bool = False, bdy_scale: float = 100.0) -> Grid:
+    """Seeded 3-D grid of side n: boundary (6, n, n) U[0, bdy_scale] (faces
+    x = 0, x = n+1, y = 0, y = n+1, z = 0, z = n+1), source f (n, n, n) of
+    N(0, 1000^2) values or None, u0 (n, n, n) zero or U[0, 100]."""
+    rng = np.random.default_rng([seed, 3])
+    bdy = rng.uniform(0.0, bdy_scale, size=(6, n, n))
+    f = rng.standard_normal((n, n, n)) * 1000.0 if with_f else None
+    u0 = rng.uniform(0.0, 100.0, size=(n, n, n)) if nonzero_u0 else np.zeros((n, n, n))
+    return Grid(n, u0, bdy, f, omega_opt(n) if omega is None else omega, meta={"dims": 3})
+
+
 class ServingStream:
     """Seeded Poisson arrivals of solve requests, generated on demand.
 
