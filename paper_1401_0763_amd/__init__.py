@@ -122,6 +122,11 @@ def _declare(lib):
     for name in ("sor_solve_f64", "sor_solve_f32", "sor_solve3d_f64"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = ctypes.c_int
+    lib.sor_ctx_set_tiling3d.argtypes = [P, i32, i32, i32]
+    lib.sor_ctx_set_tiling3d.restype = ctypes.c_int
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    lib.sor_ctx_tiling3d_for.argtypes = [P, i32, i32, pi32, pi32, pi32]
+    lib.sor_ctx_tiling3d_for.restype = ctypes.c_int
     lib.sor_residual_f64.argtypes = [P, P, P, P, i32, P, P, P]
     lib.sor_residual_f64.restype = ctypes.c_int
     lib.sor_solve_mixed.argtypes = [P, P, P, P, i32, dbl, dbl, i64, i32, i64, P,
@@ -204,6 +209,18 @@ class Context:
         if st not in allow:
             raise SorError(st, self.error())
         return st
+
+    def set_tiling3d(self, cx: int = 0, cy: int = 0, zs: int = 0):
+        """Core tile sizes of the 3-D streaming kernel (0: automatic)."""
+        self._check(self.lib.sor_ctx_set_tiling3d(self.handle, int(cx), int(cy), int(zs)))
+
+    def tiling3d_for(self, n: int, has_rhs: bool = False):
+        """(cx, cy, zs) a 3-D solve of side n would use."""
+        a, b, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self.lib.sor_ctx_tiling3d_for(self.handle, int(n), int(bool(has_rhs)),
+                                                  ctypes.byref(a), ctypes.byref(b),
+                                                  ctypes.byref(z)))
+        return a.value, b.value, z.value
 
     def set_kernel(self, kernel: int):
         self._check(self.lib.sor_ctx_set_kernel(self.handle, int(kernel)))

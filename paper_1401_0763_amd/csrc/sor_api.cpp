@@ -264,18 +264,37 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   }
 }
 
-// 3-D solve: iterations (red + black launch each) in chunks of 1, 2, 4 ...
-// 64, the device verdict read back after each chunk (the 2-D loop with
-// one-iteration passes and no re-run, since a pass never overshoots).
-sor_status run_iterations3d(sor_ctx *c, double *U, const double *F, int n, double omega,
-                            const Sched &sc, hipStream_t s, sor_result *res,
-                            double *hist) {
+// Tiling of a 3-D solve of side n with the streaming kernel: the context's
+// overrides, the rest chosen so the tiles fill the resident workgroups.
+Tiling3 tiling3_for(sor_ctx *c, int n, bool pois) {
+  if (c->cus == 0) {
+    hipDeviceProp_t prop;
+    c->cus = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.multiProcessorCount
+                                                                    : 256;
+    (void)hipGetLastError();
+  }
+  int &occ = c->occ3[pois ? 1 : 0];
+  if (occ == 0) occ = std::max(1, stream3d_blocks_per_cu(pois));
+  return tiling3(n, c->tiling3d[0], c->tiling3d[1], c->tiling3d[2], occ * c->cus);
+}
+
+// 3-D solve: iterations in chunks of 1, 2, 4 ... 64 launches, the device
+// verdict read back after each chunk (the 2-D loop with one-iteration passes
+// and no re-run, since a pass never overshoots).  The streaming kernel
+// alternates A -> B and B -> A; launches after a stop exit at once, so the
+// result is in A after an even number of executed passes, else in B.  The
+// colour kernel works in place on A.
+sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, int n,
+                            double omega, const Tiling3 *t, const Sched &sc,
+                            hipStream_t s, sor_result *res, double *hist,
+                            double **result_grid) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
   long long done = 0, chunk = 1;
   res->converged = 0;
   res->iterations = sc.max_iters;
   res->final_max_delta = NAN;
+  *result_grid = A;
   for (;;) {
     const long long chunk_it0 = done;
     long long k = 0;
@@ -286,7 +305,12 @@ sor_status run_iterations3d(sor_ctx *c, double *U, const double *F, int n, doubl
         if (pst != SOR_OK) return pst;
         HIP_TRY(c, hipEventRecord(e0, s));
       }
-      HIP_TRY(c, launch_sor3d_iteration(U, F, n, omega, ctl, sc, s));
+      if (t) {
+        const bool even = (done & 1) == 0;
+        HIP_TRY(c, launch_sor3d_stream(even ? A : B, even ? B : A, F, n, omega, *t, ctl, sc, s));
+      } else {
+        HIP_TRY(c, launch_sor3d_iteration(A, F, n, omega, ctl, sc, s));
+      }
       if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
       done += 1;
       if (done - chunk_it0 >= kHistCap - 1) { ++k; break; }
@@ -295,6 +319,8 @@ sor_status run_iterations3d(sor_ctx *c, double *U, const double *F, int n, doubl
     HIP_TRY(c, hipStreamSynchronize(s));
     const Ctl &h = *c->host_ctl;
     const long long hist_end = h.stop ? h.stop_iter : done;
+    if (t && (h.passes_done & 1)) *result_grid = B;
+    else *result_grid = A;
     if (c->prof) {
       for (long long j = 0; j < k; ++j) {
         if (h.stop && chunk_it0 + j >= h.stop_iter) break;    // exited early
@@ -504,22 +530,62 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
   if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
   if ((st = check_sched(c, tol, max_iters, check_every)) != SOR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
+  Tiling3 t{};
+  if (!simple) {
+    t = tiling3_for(c, n, rhs != nullptr);
+    if (!t.ok)
+      return fail(c, SOR_EINVAL, "3-D tile region %d x %d exceeds one workgroup's positions",
+                  t.RX, t.RY);
+  }
   const size_t elems = (size_t)grid3_pitch(n) * (size_t)(n + 2) * (size_t)(n + 2);
   if ((st = ensure(c, kGridA64, elems * sizeof(double)))) return st;
+  if (!simple && (st = ensure(c, kGridB64, elems * sizeof(double)))) return st;
   if (rhs && (st = ensure(c, kF64Buf, elems * sizeof(double)))) return st;
-  double *U = (double *)c->bufs[kGridA64].p;
+  double *A = (double *)c->bufs[kGridA64].p;
+  double *B = simple ? nullptr : (double *)c->bufs[kGridB64].p;
   double *F = rhs ? (double *)c->bufs[kF64Buf].p : nullptr;
   unsigned *bad = &((Ctl *)c->bufs[kCtlBuf].p)->input_nonfinite;
-  HIP_TRY(c, launch_pack3d(u, bdy, rhs, U, F, n, bad, s));
+  HIP_TRY(c, launch_pack3d(u, bdy, rhs, A, B, F, n, bad, s));
   *out = sor_result{};
   out->rel_residual = NAN;
   const Sched sc{max_iters, check_every, tol};
-  st = run_iterations3d(c, U, F, n, omega, sc, s, out, hist);
+  double *res_grid = A;
+  st = run_iterations3d(c, A, B, F, n, omega, simple ? nullptr : &t, sc, s, out, hist,
+                        &res_grid);
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
-    HIP_TRY(c, launch_unpack3d(U, u, n, s));
+    HIP_TRY(c, launch_unpack3d(res_grid, u, n, s));
     HIP_TRY(c, hipStreamSynchronize(s));
   }
   return st;
+}
+
+sor_status sor_ctx_set_tiling3d(sor_ctx *c, int32_t cx, int32_t cy, int32_t zs) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (cx < 0 || cy < 0 || zs < 0)
+    return fail(c, SOR_EINVAL, "3-D tiling (%d, %d, %d): sizes must be >= 0", cx, cy, zs);
+  if (cx > 0 && (cx + 4) * 5 > 2048)
+    return fail(c, SOR_EINVAL, "3-D tiling: cx = %d leaves no room for a row of tiles", cx);
+  if (cx > 0 && cy > 0 && (cx + 4) * (cy + 4) > 2048)
+    return fail(c, SOR_EINVAL, "3-D tiling: (%d + 4) x (%d + 4) positions exceed 2048", cx, cy);
+  c->tiling3d[0] = cx;
+  c->tiling3d[1] = cy;
+  c->tiling3d[2] = zs;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_tiling3d_for(sor_ctx *c, int32_t n, int32_t has_rhs, int32_t *cx,
+                                int32_t *cy, int32_t *zs) {
+  if (!c || !cx || !cy || !zs) return SOR_EINVAL;
+  c->err.clear();
+  if (n < 1 || n > kMaxN3) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN3);
+  HIP_TRY(c, hipSetDevice(c->device));
+  const Tiling3 t = tiling3_for(c, n, has_rhs != 0);
+  *cx = t.CX;
+  *cy = t.CY;
+  *zs = t.Zs;
+  return t.ok ? SOR_OK : fail(c, SOR_EINVAL, "3-D tile region %d x %d too large", t.RX, t.RY);
 }
 
 sor_status sor_residual_f64(sor_ctx *c, const double *u, const double *bdy,

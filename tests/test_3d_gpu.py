@@ -56,17 +56,30 @@ def run3(sor, ctx, g, tol, iters, K, hist=True):
     return res, u.cpu().numpy()
 
 
+# Streaming-kernel tilings (core cx, cy, zs; 0 = automatic): ragged strips,
+# bands and z-ranges, one-plane ranges, the widest strips.
+TILINGS3 = [(0, 0, 0), (3, 2, 2), (4, 3, 3), (7, 5, 1), (124, 0, 0), (30, 11, 5), (0, 0, 64)]
+
+
 @pytest.mark.parametrize("n,with_f,iters", [
     (1, True, 5), (2, False, 7), (3, True, 9), (5, True, 11), (16, False, 13),
     (33, True, 17), (64, True, 6), (67, False, 9), (130, True, 4)])
 def test_fixed_iterations_bitwise(sor, ctx, n, with_f, iters):
     g = random_cube(300 + n, n, with_f=with_f, nonzero_u0=True)
-    _say(f"3d n={n} f={with_f} iters={iters}")
     ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, g.omega, 0.0, iters, 1, threads=8, hist=True)
+    for cx, cy, zs in TILINGS3:
+        _say(f"3d stream n={n} f={with_f} iters={iters} tiling=({cx},{cy},{zs})")
+        ctx.set_tiling3d(cx, cy, zs)
+        res, u = run3(sor, ctx, g, 0.0, iters, 1)
+        assert res.status == sor.NOT_CONVERGED and res.iterations == iters
+        assert_bitwise(u, ref.u, f"u n={n} tiling=({cx},{cy},{zs})")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} tiling=({cx},{cy},{zs})")
+    _say(f"3d colour kernel n={n}")
+    ctx.set_tiling3d(0, 0, 0)
+    ctx.set_kernel(sor.KERNEL_SIMPLE)
     res, u = run3(sor, ctx, g, 0.0, iters, 1)
-    assert res.status == sor.NOT_CONVERGED and res.iterations == iters
-    assert_bitwise(u, ref.u, f"u n={n}")
-    assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n}")
+    assert_bitwise(u, ref.u, f"u n={n} colour kernel")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} colour kernel")
 
 
 @pytest.mark.parametrize("omega", [0.376, 1.0, 1.5, 1.95])
@@ -82,10 +95,12 @@ def test_omega_values_bitwise(sor, ctx, omega):
 @pytest.mark.parametrize("K", [1, 5, 10])
 def test_to_tolerance_same_stop(sor, ctx, K):
     """Converges; stops at the same checked iteration with the same change
-    and the same grid (the chunked host loop never overshoots the stop)."""
+    and the same grid (the chunked host loop never overshoots the stop, and
+    the result is taken from whichever grid the last executed pass wrote:
+    tolerances met at odd and at even iterations)."""
     n = 24
     g = random_cube(11, n, with_f=False)
-    for tol in (1e-3, 1e-8):
+    for tol in (1e-3, 1e-5, 1e-8):
         _say(f"3d tol={tol} K={K}")
         ref = oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, tol, 100000, K, threads=8, hist=True)
         assert ref.status == oracle.OK
@@ -120,6 +135,17 @@ def test_sampled_cells_at_256_against_converged_oracle(sor, ctx):
     res, u = run3(sor, ctx, g, 0.0, iters, 1)
     assert_bitwise(u, ref.u, "u n=256")
     assert_bitwise(np.array(res.hist), ref.mhist, "hist n=256")
+
+
+def test_tiling3d_reporting_and_rejection(sor, ctx):
+    cx, cy, zs = ctx.tiling3d_for(256)
+    assert (cx + 4) * (cy + 4) <= 2048 and 1 <= zs <= 256
+    ctx.set_tiling3d(30, 11, 5)
+    assert ctx.tiling3d_for(256) == (29, 11, 5)       # 9 equal strips of <= 30
+    for bad in ((-1, 0, 0), (0, -2, 0), (0, 0, -3), (500, 0, 0), (60, 60, 0)):
+        with pytest.raises(sor.SorError):
+            ctx.set_tiling3d(*bad)
+    ctx.set_tiling3d(0, 0, 0)
 
 
 def test_nonfinite_input_and_invalid_arguments(sor, ctx):
