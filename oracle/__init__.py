@@ -69,6 +69,10 @@ def _load():
                                      ctypes.c_double, ctypes.c_int64,
                                      ctypes.c_int64, ctypes.c_int, i64p, dp, dp]
     lib.oracle_sor3d_f64.restype = ctypes.c_int
+    lib.oracle_variant_f64.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp,
+                                       ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                       ctypes.c_int64, i64p, dp, dp]
+    lib.oracle_variant_f64.restype = ctypes.c_int
     lib.oracle_round_half.argtypes = [ctypes.c_float]
     lib.oracle_round_half.restype = ctypes.c_float
     _lib = lib
@@ -200,6 +204,33 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
         raise ValueError(f"oracle_mixed rejected its arguments (status {st})")
     return MixedResult(u, st, outer.value, rel.value, rh[: outer.value + 1],
                        corr.value)
+
+
+ORDER_JACOBI = 1
+ORDER_FOUR_COLOUR = 2
+
+
+def variant_f64(ordering, u0, bdy, f, omega, tol, max_iters, check_every=1,
+                hist=False) -> SorResult:
+    """FP64 Jacobi (ordering 1: every cell from the previous iterate, w = 1
+    plain Jacobi) or four-colour SOR (ordering 2: colours 2*(i mod 2) + (j mod
+    2) of the full array updated in the order 0, 1, 2, 3), same update, stop
+    rule and array conventions as sor_f64."""
+    lib = _load()
+    n = int(np.asarray(bdy).size // 4)
+    u, b, ff = _grid_args(n, u0, bdy, f, np.float64)
+    it = ctypes.c_int64(0)
+    mx = ctypes.c_double(0.0)
+    mh = np.zeros(max_iters, dtype=np.float64) if hist else None
+    st = lib.oracle_variant_f64(int(ordering), n, _ptr(u, ctypes.c_double),
+                                _ptr(b, ctypes.c_double), _ptr(ff, ctypes.c_double),
+                                float(omega), float(tol), int(max_iters), int(check_every),
+                                ctypes.byref(it), ctypes.byref(mx), _ptr(mh, ctypes.c_double))
+    if st < 0 and st != ENONFINITE:
+        raise ValueError(f"oracle_variant_f64 rejected its arguments (status {st})")
+    if mh is not None:
+        mh = mh[: it.value]
+    return SorResult(u, st, it.value, mx.value, mh)
 
 
 def sor3d_f64(u0, bdy, f, omega, tol, max_iters, check_every=1, threads=1,

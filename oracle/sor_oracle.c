@@ -3,7 +3,8 @@
  * over-relaxation (SOR) on the 5-point discretisation of the 2-D steady-state
  * heat conduction problem with Dirichlet boundaries (Mittal, "A Study of
  * Successive Over-relaxation Method Parallelization Over Modern HPC
- * Languages", 2014), and on the 7-point discretisation of its 3-D form (the
+ * Languages", 2014), the Jacobi and four-colour alternatives it names
+ * (Sec. 2.1, Sec. 3.1), and the 7-point discretisation of its 3-D form (the
  * extension the paper names as future work, Sec. 5; last section below).
  *
  * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
@@ -204,6 +205,126 @@ int oracle_sor_f64(int n, double *u, const double *bdy, const double *f,
     if (iters_out) *iters_out = it;
     if (max_out) *max_out = last;
     free(U);
+    free(F);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* FP64 variants: Jacobi and the four-colour ordering                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The two alternatives to the red-black order that the paper names (Sec. 2.1
+ * introduces Jacobi as the method that uses only the previous iteration's
+ * values; Sec. 3.1 lists multi-colour SOR among the parallel versions).  Both
+ * use the same Gauss-Seidel value and increment form of Eq. 1 as
+ * oracle_sor_f64 and the same stopping rule (Algorithm 1).
+ *
+ * ORDER_JACOBI (1): every interior cell is updated from the previous
+ *   iterate, X_k = X + w*(avg(neighbours of X) - X) (w = 1 is Jacobi, other
+ *   w the over-relaxed Jacobi iteration), computed into a second array.
+ * ORDER_FOUR_COLOUR (2): cell (i, j) of the full array has colour
+ *   2*(i mod 2) + (j mod 2); an iteration updates colour 0, 1, 2, 3 in that
+ *   order, in place, each like a red-black half-sweep (no cell reads a cell
+ *   of its own colour, so the visiting order inside a colour is immaterial).
+ *
+ * Arguments, outputs and statuses as for oracle_sor_f64 (single-threaded).
+ */
+#define ORC_ORDER_JACOBI 1
+#define ORC_ORDER_FOUR_COLOUR 2
+
+/* One Jacobi iteration from U into V (interior only; V's ring is already the
+ * boundary).  Returns the max |new - old|. */
+static double orc_jacobi_sweep_f64(int n, const double *U, double *V, const double *F,
+                                   double w, int *bad)
+{
+    double m = 0.0;
+    for (int i = 1; i <= n; ++i)
+        for (int j = 1; j <= n; ++j) {
+            double old = U[AT(i, j)];
+            double s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
+                       (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
+            if (F) s = s + F[AT(i, j)];
+            double gs = 0.25 * s;
+            double nu = old + w * (gs - old);
+            double d = fabs(nu - old);
+            if (!isfinite(nu)) *bad = 1;
+            if (d > m) m = d;
+            V[AT(i, j)] = nu;
+        }
+    return m;
+}
+
+/* Update the cells of colour c (rows i = c/2 mod 2, columns j = c mod 2) of
+ * U in place.  Returns the max |new - old| over them. */
+static double orc_colour4_sweep_f64(int n, double *U, const double *F, double w, int c,
+                                    int *bad)
+{
+    double m = 0.0;
+    int i0 = (c >> 1) ? 1 : 2, j0 = (c & 1) ? 1 : 2;
+    for (int i = i0; i <= n; i += 2)
+        for (int j = j0; j <= n; j += 2) {
+            double old = U[AT(i, j)];
+            double s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
+                       (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
+            if (F) s = s + F[AT(i, j)];
+            double gs = 0.25 * s;
+            double nu = old + w * (gs - old);
+            double d = fabs(nu - old);
+            if (!isfinite(nu)) *bad = 1;
+            if (d > m) m = d;
+            U[AT(i, j)] = nu;
+        }
+    return m;
+}
+
+int oracle_variant_f64(int ordering, int n, double *u, const double *bdy, const double *f,
+                       double omega, double tol, int64_t max_iters, int64_t check_every,
+                       int64_t *iters_out, double *max_out, double *mhist)
+{
+    if ((ordering != ORC_ORDER_JACOBI && ordering != ORC_ORDER_FOUR_COLOUR) || n < 1 ||
+        !u || !bdy || !(omega > 0.0 && omega < 2.0) || !(tol >= 0.0) || max_iters < 1 ||
+        check_every < 1)
+        return ORC_EINVAL;
+    size_t cells = (size_t)(n + 2) * (size_t)(n + 2);
+    double *U = malloc(sizeof(double) * cells);
+    double *V = ordering == ORC_ORDER_JACOBI ? malloc(sizeof(double) * cells) : NULL;
+    double *F = orc_make_F(n, f);
+    if (!U || (ordering == ORC_ORDER_JACOBI && !V) || (f && !F)) {
+        free(U); free(V); free(F);
+        return ORC_ENOMEM;
+    }
+    orc_fill_f64(n, U, u, bdy);
+    if (V) memcpy(V, U, sizeof(double) * cells);
+
+    int status = ORC_NOT_CONVERGED;
+    int64_t it = 0;
+    double last = NAN;
+    for (it = 1; it <= max_iters; ++it) {
+        double m = 0.0;
+        int bad = 0;
+        if (ordering == ORC_ORDER_JACOBI) {
+            m = orc_jacobi_sweep_f64(n, U, V, F, omega, &bad);
+            double *t = U; U = V; V = t;
+        } else {
+            for (int c = 0; c < 4; ++c) {
+                double mc = orc_colour4_sweep_f64(n, U, F, omega, c, &bad);
+                if (mc > m) m = mc;
+            }
+        }
+        if (mhist) mhist[it - 1] = m;
+        if (bad) { status = ORC_ENONFINITE; last = m; break; }
+        if (it % check_every == 0 || it == max_iters) {
+            last = m;
+            if (m < tol) { status = ORC_OK; break; }
+        }
+    }
+    if (it > max_iters) it = max_iters;
+    orc_extract_f64(n, U, u);
+    if (iters_out) *iters_out = it;
+    if (max_out) *max_out = last;
+    free(U);
+    free(V);
     free(F);
     return status;
 }
