@@ -336,6 +336,54 @@ def form_3d(sor, ctx, torch, n=256, iters=1000):
     return out
 
 
+def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128):
+    """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1): update rate
+    on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
+    around each iteration's launches; 16 algorithmic bytes per update against
+    the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
+    128^2 grid next to red-black, all at their best omega (Jacobi: 1)."""
+    from workloads import laplace_random_boundary
+    g = laplace_random_boundary(n)
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    out = {"workload": f"laplace_random_boundary_{n}, {iters} iterations; "
+                       f"laplace_random_boundary_{n_conv} to 1e-8"}
+    for ordering, name, omega in ((sor.ORDER_JACOBI, "jacobi", 1.0),
+                                  (sor.ORDER_FOUR_COLOUR, "four_colour", g.omega)):
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        sor.solve_variant_f64(ordering, u, b, None, omega, 0.0, 10, 10, ctx=ctx)
+        u.zero_()
+        ctx.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sor.solve_variant_f64(ordering, u, b, None, omega, 0.0, iters, 10, ctx=ctx)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kern_ms, launches = ctx.profile()
+        ctx.set_profiling(False)
+        it_us = kern_ms * 1e3 / max(launches, 1)
+        out[name] = {"glups": round(n * n * r.iterations / dt / 1e9, 1),
+                     "us_per_iteration": round(it_us, 2),
+                     "glups_kernel": round(n * n / (it_us * 1e-6) / 1e9, 1),
+                     "hbm_equiv_GBs": round(BYTES_PER_LUP_F64 * n * n / (it_us * 1e-6) / 1e9, 1),
+                     "hbm_frac": round(BYTES_PER_LUP_F64 * n * n / (it_us * 1e-6) / 1e9
+                                       / HBM_PEAK_GBS, 3)}
+    gc = laplace_random_boundary(n_conv)
+    bc = torch.tensor(gc.bdy, dtype=torch.float64, device="cuda")
+    conv = {}
+    for ordering, name, omega in ((sor.ORDER_RED_BLACK, "red_black", gc.omega),
+                                  (sor.ORDER_FOUR_COLOUR, "four_colour", gc.omega),
+                                  (sor.ORDER_JACOBI, "jacobi", 1.0)):
+        u = torch.zeros((n_conv, n_conv), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sor.solve_variant_f64(ordering, u, bc, None, omega, 1e-8, 1000000, 10, ctx=ctx)
+        torch.cuda.synchronize()
+        conv[name] = {"converged": bool(r.converged), "iterations": r.iterations,
+                      "secs": round(time.perf_counter() - t0, 3)}
+    out["to_1e-8"] = conv
+    return out
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs), q))
@@ -425,7 +473,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="tol,paper,mixed,batched,3d,serving",
+    ap.add_argument("--forms", default="tol,paper,mixed,batched,3d,variants,serving",
                     help="comma list of extra forms to measure, or 'none'")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-burst", type=int, default=80)
@@ -532,6 +580,9 @@ def main():
     if "batched" in forms:
         print("[bench] form: batched 512 grids", file=sys.stderr, flush=True)
         line["forms"]["batched"] = form_batched(sor, ctx, torch)
+    if "variants" in forms:
+        print("[bench] form: Jacobi and four-colour orderings", file=sys.stderr, flush=True)
+        line["forms"]["variants"] = form_variants(sor, ctx, torch)
     if "3d" in forms:
         print("[bench] form: 3-D 256^3", file=sys.stderr, flush=True)
         line["forms"]["3d"] = form_3d(sor, ctx, torch)

@@ -194,6 +194,35 @@ sor_status sor_solve3d_f64(sor_ctx *ctx, double *u, const double *boundary,
                            sor_result *out, double *max_hist);
 
 /*
+ * Orderings of the 2-D FP64 solve.  RED_BLACK is the paper's method
+ * (Sec. 3.1).  JACOBI updates every interior cell from the previous iterate
+ * (the method Sec. 2.1 contrasts SOR with; omega = 1 is plain Jacobi, other
+ * omega the over-relaxed Jacobi iteration).  FOUR_COLOUR is the multi-colour
+ * SOR that Sec. 3.1 names, with colour(i, j) = 2 (i mod 2) + (j mod 2) on the
+ * full array (boundary at index 0) and the colours swept in the order
+ * 0, 1, 2, 3 (in place; colours 1 and 2 never touch, so they share a launch).
+ */
+enum {
+  SOR_ORDER_RED_BLACK = 0,
+  SOR_ORDER_JACOBI = 1,
+  SOR_ORDER_FOUR_COLOUR = 2
+};
+
+/*
+ * sor_solve_f64 with the given ordering: same arguments, layout, ownership,
+ * update expression ((N+S)+(W+E) [+h*h*f]) * 0.25 in increment form,
+ * stopping rule (Algorithm 1), results and errors; SOR_EINVAL for an unknown
+ * ordering.  JACOBI and FOUR_COLOUR run one iteration per pass (JACOBI: one
+ * launch from one padded grid into a second; FOUR_COLOUR: three launches in
+ * place), and ignore the context's kernel and tiling settings.
+ */
+sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
+                                 const double *boundary, const double *rhs, int32_t n,
+                                 double omega, double tol, int64_t max_iters,
+                                 int64_t check_every, void *stream, sor_result *out,
+                                 double *max_hist);
+
+/*
  * Tiling of sor_solve3d_f64's streaming kernel (not in the paper; results do
  * not depend on it).  A tile is a core of cx x cy cells in x and y and zs
  * planes in z, one workgroup of 256 threads; the workgroup holds the core

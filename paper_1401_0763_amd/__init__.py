@@ -122,6 +122,8 @@ def _declare(lib):
     for name in ("sor_solve_f64", "sor_solve_f32", "sor_solve3d_f64"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = ctypes.c_int
+    lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
+    lib.sor_solve_variant_f64.restype = ctypes.c_int
     lib.sor_ctx_set_tiling3d.argtypes = [P, i32, i32, i32]
     lib.sor_ctx_set_tiling3d.restype = ctypes.c_int
     pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -389,6 +391,33 @@ def solve_f32(u, boundary, rhs=None, omega=None, tol=1e-5, max_iters=100000,
     ctx = ctx or context(u.device.index)
     return _solve_plain(ctx.lib.sor_solve_f32, torch.float32, u, boundary, rhs,
                         omega, tol, max_iters, check_every, hist, ctx)
+
+
+ORDER_RED_BLACK, ORDER_JACOBI, ORDER_FOUR_COLOUR = 0, 1, 2
+
+
+def solve_variant_f64(ordering, u, boundary, rhs=None, omega=None, tol=1e-8,
+                      max_iters=100000, check_every=1, hist=False,
+                      ctx: Context | None = None) -> Result:
+    """FP64 solve in place on u with the given ordering (ORDER_RED_BLACK,
+    ORDER_JACOBI or ORDER_FOUR_COLOUR); otherwise as solve_f64."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = 1.0 if ordering == ORDER_JACOBI else 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    pu = _check_tensor("u", u, torch.float64, (n, n))
+    pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
+    ctx = ctx or context(u.device.index)
+    res = _Result()
+    hbuf = (ctypes.c_double * int(max_iters))() if hist else None
+    st = ctx.lib.sor_solve_variant_f64(ctx.handle, int(ordering), pu, pb, pf, int(n),
+                                       float(omega), float(tol), int(max_iters),
+                                       int(check_every), _stream_handle(u),
+                                       ctypes.byref(res), hbuf)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    h = list(hbuf[: res.iterations]) if hist else None
+    return _result(st, res, h)
 
 
 def solve3d_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,

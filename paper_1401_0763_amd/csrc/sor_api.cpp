@@ -25,6 +25,7 @@
 
 #include "sor_host.h"
 #include "sor_3d.h"
+#include "sor_variants.h"
 
 using namespace sor;
 
@@ -278,23 +279,23 @@ Tiling3 tiling3_for(sor_ctx *c, int n, bool pois) {
   return tiling3(n, c->tiling3d[0], c->tiling3d[1], c->tiling3d[2], occ * c->cus);
 }
 
-// 3-D solve: iterations in chunks of 1, 2, 4 ... 64 launches, the device
+// Solves whose every pass is one iteration (the 3-D kernels, the Jacobi and
+// four-colour orderings): iterations in chunks of 1, 2, 4 ... 64, the device
 // verdict read back after each chunk (the 2-D loop with one-iteration passes
-// and no re-run, since a pass never overshoots).  The streaming kernel
-// alternates A -> B and B -> A; launches after a stop exit at once, so the
-// result is in A after an even number of executed passes, else in B.  The
-// colour kernel works in place on A.
-sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, int n,
-                            double omega, const Tiling3 *t, const Sched &sc,
-                            hipStream_t s, sor_result *res, double *hist,
-                            double **result_grid) {
+// and no re-run, since a pass never overshoots).  launch(k) enqueues
+// iteration k (0-based) on s.  Launches after a stop exit at once, so a
+// ping-pong solve's result is in its first grid after an even number of
+// executed passes (res->passes), else in its second.
+template <class Launch>
+sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_result *res,
+                              double *hist, Launch launch) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
   long long done = 0, chunk = 1;
   res->converged = 0;
   res->iterations = sc.max_iters;
   res->final_max_delta = NAN;
-  *result_grid = A;
+  res->passes = 0;
   for (;;) {
     const long long chunk_it0 = done;
     long long k = 0;
@@ -305,12 +306,7 @@ sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, i
         if (pst != SOR_OK) return pst;
         HIP_TRY(c, hipEventRecord(e0, s));
       }
-      if (t) {
-        const bool even = (done & 1) == 0;
-        HIP_TRY(c, launch_sor3d_stream(even ? A : B, even ? B : A, F, n, omega, *t, ctl, sc, s));
-      } else {
-        HIP_TRY(c, launch_sor3d_iteration(A, F, n, omega, ctl, sc, s));
-      }
+      HIP_TRY(c, launch(done));
       if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
       done += 1;
       if (done - chunk_it0 >= kHistCap - 1) { ++k; break; }
@@ -319,8 +315,7 @@ sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, i
     HIP_TRY(c, hipStreamSynchronize(s));
     const Ctl &h = *c->host_ctl;
     const long long hist_end = h.stop ? h.stop_iter : done;
-    if (t && (h.passes_done & 1)) *result_grid = B;
-    else *result_grid = A;
+    res->passes = h.passes_done;
     if (c->prof) {
       for (long long j = 0; j < k; ++j) {
         if (h.stop && chunk_it0 + j >= h.stop_iter) break;    // exited early
@@ -336,7 +331,6 @@ sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, i
     if (h.stop) {
       res->iterations = h.stop_iter;
       res->final_max_delta = h.stop_max;
-      res->passes = h.passes_done;
       if (h.stop == 2)
         return fail(c, SOR_ENONFINITE, "non-finite value in the grid by iteration %lld",
                     h.stop_iter);
@@ -345,11 +339,26 @@ sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, i
     }
     if (done >= sc.max_iters) {
       res->final_max_delta = h.last_max;
-      res->passes = h.passes_done;
       return SOR_NOT_CONVERGED;
     }
     chunk = std::min<long long>(chunk * 2, 64);
   }
+}
+
+// 3-D solve: the streaming kernel alternates A -> B and B -> A; the colour
+// kernel (t == nullptr) works in place on A.
+sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, int n,
+                            double omega, const Tiling3 *t, const Sched &sc,
+                            hipStream_t s, sor_result *res, double *hist,
+                            double **result_grid) {
+  Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
+  const sor_status st = run_iteration_loop(c, sc, s, res, hist, [&](long long k) {
+    if (!t) return launch_sor3d_iteration(A, F, n, omega, ctl, sc, s);
+    const bool even = (k & 1) == 0;
+    return launch_sor3d_stream(even ? A : B, even ? B : A, F, n, omega, *t, ctl, sc, s);
+  });
+  *result_grid = (t && (res->passes & 1)) ? B : A;
+  return st;
 }
 
 sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K) {
@@ -555,6 +564,50 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
                         &res_grid);
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack3d(res_grid, u, n, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+  }
+  return st;
+}
+
+sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const double *bdy,
+                                 const double *rhs, int32_t n, double omega, double tol,
+                                 int64_t max_iters, int64_t check_every, void *stream,
+                                 sor_result *out, double *hist) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (ordering == SOR_ORDER_RED_BLACK)
+    return sor_solve_f64(c, u, bdy, rhs, n, omega, tol, max_iters, check_every, stream, out,
+                         hist);
+  if (ordering != SOR_ORDER_JACOBI && ordering != SOR_ORDER_FOUR_COLOUR)
+    return fail(c, SOR_EINVAL, "unknown ordering %d", ordering);
+  sor_status st = check_common(c, u, bdy, rhs, n, omega);
+  if (st != SOR_OK) return st;
+  if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
+  if ((st = check_sched(c, tol, max_iters, check_every)) != SOR_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const Layout L = make_layout(n, kF64);
+  const size_t bytes = (size_t)L.elems() * sizeof(double);
+  const bool jacobi = ordering == SOR_ORDER_JACOBI;
+  if ((st = ensure(c, kGridA64, bytes)) || (st = ensure(c, kGridB64, bytes))) return st;
+  if (rhs && (st = ensure(c, kF64Buf, bytes))) return st;
+  double *A = origin<double>(c, kGridA64, L), *B = origin<double>(c, kGridB64, L);
+  double *F = rhs ? origin<double>(c, kF64Buf, L) : nullptr;
+  Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
+  unsigned *bad = &ctl->input_nonfinite;
+  HIP_TRY(c, launch_pack(kF64, u, bdy, A, B, L.pitch, n, bad, s));
+  if (rhs) HIP_TRY(c, launch_pack_rhs(kF64, rhs, F, L.pitch, n, bad, s));
+  *out = sor_result{};
+  out->rel_residual = NAN;
+  const Sched sc{max_iters, check_every, tol};
+  st = run_iteration_loop(c, sc, s, out, hist, [&](long long k) {
+    if (!jacobi) return launch_colour4_iteration(A, F, L.pitch, n, omega, ctl, sc, s);
+    const bool even = (k & 1) == 0;
+    return launch_jacobi_iteration(even ? A : B, even ? B : A, F, L.pitch, n, omega, ctl, sc,
+                                   s);
+  });
+  const double *res_grid = (jacobi && (out->passes & 1)) ? B : A;
+  if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
+    HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));
     HIP_TRY(c, hipStreamSynchronize(s));
   }
   return st;
