@@ -295,7 +295,7 @@ def form_paper(sor, ctx, torch, n=4096):
             "glups": round(n * n * r.iterations / dt / 1e9, 1)}
 
 
-def form_3d(sor, ctx, torch, n=256, iters=1000):
+def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
     """The 3-D extension (7-point stencil on the unit cube): 256^3 interior
     cells, random boundary faces, omega_opt; a fixed iteration count for the
     update rate (kernel time from HIP events around each launch), then a
@@ -333,10 +333,19 @@ def form_3d(sor, ctx, torch, n=256, iters=1000):
     torch.cuda.synchronize()
     out["tol_1e-8"] = {"converged": bool(r.converged), "iterations": r.iterations,
                        "secs": round(time.perf_counter() - t0, 3)}
+    if cpu:
+        import oracle
+        threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+        iters_cpu = 40
+        t0 = time.perf_counter()
+        oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, 0.0, iters_cpu, 10, threads=threads)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"glups": round(n ** 3 * iters_cpu / dt / 1e9, 3), "cores": threads,
+                             "sample": f"same {n}^3 grid, {iters_cpu} iterations, {dt:.1f} s"}
     return out
 
 
-def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128):
+def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
     """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1): update rate
     on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
     around each iteration's launches; 16 algorithmic bytes per update against
@@ -381,6 +390,18 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128):
         conv[name] = {"converged": bool(r.converged), "iterations": r.iterations,
                       "secs": round(time.perf_counter() - t0, 3)}
     out["to_1e-8"] = conv
+    if cpu:
+        import oracle
+        iters_cpu = 8
+        for ordering, name, omega in ((sor.ORDER_JACOBI, "jacobi", 1.0),
+                                      (sor.ORDER_FOUR_COLOUR, "four_colour", g.omega)):
+            t0 = time.perf_counter()
+            oracle.variant_f64(ordering, g.u0, g.bdy, None, omega, 0.0, iters_cpu, 10)
+            dt = time.perf_counter() - t0
+            out[name]["cpu_oracle"] = {"glups": round(n * n * iters_cpu / dt / 1e9, 3),
+                                       "cores": 1,
+                                       "sample": f"same {n}^2 grid, {iters_cpu} iterations, "
+                                                 f"single thread, {dt:.1f} s"}
     return out
 
 
@@ -582,10 +603,11 @@ def main():
         line["forms"]["batched"] = form_batched(sor, ctx, torch)
     if "variants" in forms:
         print("[bench] form: Jacobi and four-colour orderings", file=sys.stderr, flush=True)
-        line["forms"]["variants"] = form_variants(sor, ctx, torch)
+        line["forms"]["variants"] = form_variants(sor, ctx, torch,
+                                                  cpu=not args.no_cpu_baseline)
     if "3d" in forms:
         print("[bench] form: 3-D 256^3", file=sys.stderr, flush=True)
-        line["forms"]["3d"] = form_3d(sor, ctx, torch)
+        line["forms"]["3d"] = form_3d(sor, ctx, torch, cpu=not args.no_cpu_baseline)
     if "serving" in forms:
         print("[bench] form: serving", file=sys.stderr, flush=True)
         line["forms"]["serving"] = form_serving(sor, ctx, torch, args.serve_requests,
