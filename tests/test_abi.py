@@ -50,3 +50,27 @@ def test_binding_loads_and_validates_without_gpu():
     assert lib.sor_ctx_set_tiling(None, 64, ctypes.byref(t)) == sor.EINVAL
     assert lib.sor_solve_f64(None, None, None, None, 8, 1.5, 1e-6, 10, 1, None,
                              None, None) == sor.EINVAL
+
+
+def test_newer_entry_points_reject_a_null_context():
+    import paper_1401_0763_amd as sor
+    lib = sor.load_library()
+    assert lib.sor_solve3d_f64(None, None, None, None, 8, 1.5, 1e-6, 10, 1, None,
+                               None, None) == sor.EINVAL
+    assert lib.sor_solve_variant_f64(None, 1, None, None, None, 8, 1.0, 1e-6, 10, 1,
+                                     None, None, None) == sor.EINVAL
+    assert lib.sor_ctx_set_tiling3d(None, 0, 0, 0) == sor.EINVAL
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.sor_ctx_tiling3d_for(None, 64, 0, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)) == sor.EINVAL
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the shared library absent the binding raises."""
+    import paper_1401_0763_amd as sor
+    monkeypatch.setattr(sor, "LIB_PATH", str(tmp_path / "libsor.so"))
+    monkeypatch.setattr(sor, "_lib", None)
+    with pytest.raises(ImportError):
+        sor.load_library()
+    with pytest.raises(ImportError):
+        sor.version()
