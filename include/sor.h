@@ -182,11 +182,14 @@ sor_status sor_solve_f32(sor_ctx *ctx, float *u, const float *boundary,
  *   n in 1..1024; other arguments, results and errors as for sor_solve_f64
  *   (out->passes counts iterations; max_hist, if not NULL, HOST max_iters
  *   doubles).
- * With SOR_KERNEL_BLOCKED (default) one launch applies a whole iteration
- * from one padded grid into a second (tiles streamed plane by plane, see
- * sor_ctx_set_tiling3d); the context holds two (n+2)^3 FP64 grids plus one
- * for rhs.  With SOR_KERNEL_SIMPLE one launch per colour works in place on
- * one grid.  Results are bit-identical either way.
+ * With SOR_KERNEL_BLOCKED (default) one launch applies one or two whole
+ * iterations from one padded grid into a second (tiles streamed plane by
+ * plane, see sor_ctx_set_tiling3d): two when check_every is even (every
+ * check then falls at the end of a launch; an odd max_iters ends with a
+ * one-iteration launch), else one.  The context holds two (n+2)^3 FP64 grids
+ * plus one for rhs.  With SOR_KERNEL_SIMPLE one launch per colour works in
+ * place on one grid.  Results are bit-identical either way; out->passes
+ * counts launches of the streaming kernel (iterations of the simple one).
  */
 sor_status sor_solve3d_f64(sor_ctx *ctx, double *u, const double *boundary,
                            const double *rhs, int32_t n, double omega, double tol,
@@ -224,23 +227,28 @@ sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
 
 /*
  * Tiling of sor_solve3d_f64's streaming kernel (not in the paper; results do
- * not depend on it).  A tile is a core of cx x cy cells in x and y and zs
- * planes in z, one workgroup of 256 threads; the workgroup holds the core
- * plus a ring of 2 cells, (cx + 4) x (cy + 4) <= 2048 positions.  0 for any
- * size picks it per solve: equal strips and bands with the fewest positions
- * per core cell, then zs so that the tiles fill whole rounds of the device's
- * resident workgroups.  Errors: SOR_EINVAL for negative sizes or a region
- * above 2048 positions (a cx with a region check that can only fail at solve
- * time is reported there).
+ * not depend on it).  iters_per_launch: 1, 2, or 0 for the default (2 when
+ * check_every is even, else 1; a 2 is honoured only then).  A tile is a core
+ * of cx x cy cells in x and y and zs planes in z, one workgroup of 256
+ * threads; the workgroup holds the core plus a ring of 2 cells per
+ * iteration: (cx + 4) x (cy + 4) <= 2048 positions for one iteration,
+ * (cx + 8) x (cy + 8) <= 2032 for two.  0 for any size picks it per solve:
+ * equal strips and bands with the fewest positions per core cell, then zs so
+ * that the tiles fill whole rounds of the device's resident workgroups.
+ * Errors: SOR_EINVAL for values out of range or a region above the limit (a
+ * region check that depends on n is reported by the solve).
  */
-sor_status sor_ctx_set_tiling3d(sor_ctx *ctx, int32_t cx, int32_t cy, int32_t zs);
+sor_status sor_ctx_set_tiling3d(sor_ctx *ctx, int32_t iters_per_launch, int32_t cx,
+                                int32_t cy, int32_t zs);
 
 /*
- * The streaming tiling a sor_solve3d_f64 of side n (with a source if has_rhs
- * is non-zero) would use, as the core sizes of its tiles (HOST outputs).
+ * The streaming set-up a sor_solve3d_f64 of side n (with a source if has_rhs
+ * is non-zero) and the given check_every would use: iterations per launch
+ * and the core sizes of its tiles (HOST outputs).
  */
-sor_status sor_ctx_tiling3d_for(sor_ctx *ctx, int32_t n, int32_t has_rhs, int32_t *cx,
-                                int32_t *cy, int32_t *zs);
+sor_status sor_ctx_tiling3d_for(sor_ctx *ctx, int32_t n, int32_t has_rhs, int64_t check_every,
+                                int32_t *iters_per_launch, int32_t *cx, int32_t *cy,
+                                int32_t *zs);
 
 /*
  * FP64 residual of the h*h-scaled system 4u - (interior neighbours) = b,

@@ -124,10 +124,10 @@ def _declare(lib):
         getattr(lib, name).restype = ctypes.c_int
     lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
     lib.sor_solve_variant_f64.restype = ctypes.c_int
-    lib.sor_ctx_set_tiling3d.argtypes = [P, i32, i32, i32]
+    lib.sor_ctx_set_tiling3d.argtypes = [P, i32, i32, i32, i32]
     lib.sor_ctx_set_tiling3d.restype = ctypes.c_int
     pi32 = ctypes.POINTER(ctypes.c_int32)
-    lib.sor_ctx_tiling3d_for.argtypes = [P, i32, i32, pi32, pi32, pi32]
+    lib.sor_ctx_tiling3d_for.argtypes = [P, i32, i32, i64, pi32, pi32, pi32, pi32]
     lib.sor_ctx_tiling3d_for.restype = ctypes.c_int
     lib.sor_residual_f64.argtypes = [P, P, P, P, i32, P, P, P]
     lib.sor_residual_f64.restype = ctypes.c_int
@@ -212,17 +212,20 @@ class Context:
             raise SorError(st, self.error())
         return st
 
-    def set_tiling3d(self, cx: int = 0, cy: int = 0, zs: int = 0):
-        """Core tile sizes of the 3-D streaming kernel (0: automatic)."""
-        self._check(self.lib.sor_ctx_set_tiling3d(self.handle, int(cx), int(cy), int(zs)))
+    def set_tiling3d(self, cx: int = 0, cy: int = 0, zs: int = 0, iters: int = 0):
+        """3-D streaming kernel: core tile sizes and iterations per launch
+        (0: automatic)."""
+        self._check(self.lib.sor_ctx_set_tiling3d(self.handle, int(iters), int(cx), int(cy),
+                                                  int(zs)))
 
-    def tiling3d_for(self, n: int, has_rhs: bool = False):
-        """(cx, cy, zs) a 3-D solve of side n would use."""
-        a, b, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    def tiling3d_for(self, n: int, has_rhs: bool = False, check_every: int = 1):
+        """(iters_per_launch, cx, cy, zs) a 3-D solve of side n would use."""
+        t, a, b, z = (ctypes.c_int32() for _ in range(4))
         self._check(self.lib.sor_ctx_tiling3d_for(self.handle, int(n), int(bool(has_rhs)),
+                                                  int(check_every), ctypes.byref(t),
                                                   ctypes.byref(a), ctypes.byref(b),
                                                   ctypes.byref(z)))
-        return a.value, b.value, z.value
+        return t.value, a.value, b.value, z.value
 
     def set_kernel(self, kernel: int):
         self._check(self.lib.sor_ctx_set_kernel(self.handle, int(kernel)))

@@ -100,37 +100,53 @@ __global__ __launch_bounds__(kX3 * kY3) void sor3d_colour_kernel(Grid3 g, Ctl *c
 }
 
 // ---------------------------------------------------------------------------
-// Streaming kernel.  Tile = core [x0, x0+CX) x [y0, y0+CY) x [z0, z1) of
-// interior cells; region = core plus a ring of 2 cells in x and y (RX = CX+4,
-// RY = CY+4 positions), held as RX*RY positions, kK3 per thread (position
-// p = thread + kT3*k, row-major in the region).  Step s handles plane
-// zr = z0-1+s:
-//   1. write plane zr (values of the previous iteration) to LDS, barrier;
-//   2. red half-sweep of plane zr on the region minus its outer ring (the
-//      black cells it reads, in the plane from LDS and above and below from
-//      registers, are all still old);
-//   3. black half-sweep of plane zr-1 on the core (its red neighbours: plane
-//      zr-1 in LDS from step s-1, planes zr-2 and zr in registers, all new),
-//      then store the core of plane zr-1 (both colours) to B.
-// Steps run from zr = z0-1 to zr = z1, so red values of planes z0-1 and z1
-// and of the ring are computed redundantly (also by the tiles that own them,
-// from the same old values, so identically) and never stored.  Three LDS
-// plane buffers (plane z in buffer z mod 3) need one barrier per step: the
-// red sweep writes red cells of buffer zr while other threads read its black
-// cells; the black sweep reads buffer zr-1 written before this step's
-// barrier; buffer zr was last read by the black sweep of step s-2.
-// Positions outside the grid load a clamped (in-bounds) address and are
-// never updated nor read by an update.
+// Streaming kernel, T iterations (S = 2T half-sweeps) per launch.  Tile =
+// core [x0, x0+CX) x [y0, y0+CY) x [z0, z1) of interior cells; region = core
+// plus a ring of S cells in x and y (RX = CX+2S, RY = CY+2S positions), held
+// as RX*RY positions, kK3 per thread (position p = thread + kT3*k,
+// row-major).  The tile walks planes upwards: step s loads plane
+// zr = z0-(S-1)+s into the pipeline and applies the S half-sweeps as stages,
+// stage k (colour k mod 2, i.e. iteration k/2's red or black phase) to plane
+// zr-k, in the order k = 0 .. S-1:
+//   - stage k at plane q needs the other colour of q at stage k-1 (done at
+//     step s-1), of q+1 (stage k-1 earlier in this step) and of q-1 (stage
+//     k-1 two steps ago; stage k+1 reaches q-1 only after stage k in this
+//     step), so every update sees exactly the two-phase iteration's values;
+//   - the dependency cone shrinks by one cell per stage, so stage k updates
+//     positions at distance >= k+1 from the region's edge and planes
+//     z0-(S-1-k) .. z1-1+(S-1-k); after the last stage the core of plane
+//     zr-(S-1) is final and stored to B.  Every value computed outside the
+//     core equals the one the tile owning that cell computes (same inputs),
+//     so all updates may enter the maxima.
+// In-plane neighbours come from LDS: plane q lives in buffer (step at which
+// stage 0 took it) mod (S+1); each stage reads one colour of its plane's
+// buffer (written by the previous stage a step earlier) and writes the other.
+// One barrier per step suffices: the buffer written before it (the new
+// plane) was last read two steps earlier, and within a step the stages touch
+// different buffers, each reading one colour and writing the other.  Planes
+// zr-S .. zr+1 and kD3 more (loads in flight) live in registers.  Positions
+// outside the grid load a clamped (in-bounds) address and are never updated
+// nor read by an update.
 // ---------------------------------------------------------------------------
 constexpr int kT3 = 256;            // threads per workgroup
 constexpr int kK3 = 8;              // positions per thread per plane
-constexpr int kP3 = kT3 * kK3;      // most positions in a region
 constexpr int kD3 = 2;              // planes loaded ahead of the one first needed
-constexpr int kW3 = kD3 + 4;        // planes in registers: zr-2 .. zr+1, plus kD3 in flight
+
+template <int T>
+struct Stream3 {
+  static constexpr int S = 2 * T;                  // stages (half-sweeps)
+  static constexpr int B = S + 1;                  // LDS plane buffers
+  static constexpr int W = S + kD3 + 2;            // register planes
+  // Most positions in a region: three buffers of 2048 (48 KB, 3 workgroups
+  // per CU) for one iteration; five of 2032 (79 KB, 2 per CU) for two.
+  static constexpr int P = T == 1 ? kT3 * kK3 : 2032;
+};
+
+int stream3d_positions(int T) { return T == 1 ? Stream3<1>::P : Stream3<2>::P; }
 
 struct Geo3 {
-  const double *A;      // iteration input
-  double *B;            // iteration output
+  const double *A;      // input of the launch
+  double *B;            // output of the launch
   const double *F;      // h*h*f or nullptr
   int64_t px, plane;    // elements per row, per plane
   int n, RX, RY, CX, CY, Zs, ntx, nty;
@@ -139,45 +155,54 @@ struct Geo3 {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-template <bool POIS>
+template <int T, bool POIS>
 __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sched sc) {
+  constexpr int S = Stream3<T>::S, B = Stream3<T>::B, W = Stream3<T>::W;
+  constexpr int PL = Stream3<T>::P;
   if (ctl_stopped(ctl)) return;
-  __shared__ double L[3][kP3];
-  __shared__ double wmax[kT3 / 64];
+  __shared__ double L[B * PL];
+  __shared__ double wmax[kT3 / 64][T];
   __shared__ int wbad[kT3 / 64];
-  const int tid = threadIdx.x, n = g.n, RX = g.RX;
+  const int tid = threadIdx.x, n = g.n, RX = g.RX, RY = g.RY;
   int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
   const int tx = tile % g.ntx;
   tile /= g.ntx;
   const int ty = tile % g.nty, tz = tile / g.nty;
   const int x0 = 1 + tx * g.CX, y0 = 1 + ty * g.CY, z0 = 1 + tz * g.Zs;
   const int z1 = min(z0 + g.Zs, n + 1);
-  const int nsteps = z1 - z0 + 2;
-  const int P = RX * g.RY;
+  const int zbeg = z0 - (S - 1);                 // stage 0's first plane
+  const int nsteps = (z1 - z0) + 2 * S - 2;
+  const int zlast = z1 + S - 1;                  // highest plane read
+  const int P = RX * RY;
   const double SIXTH = 1.0 / 6.0;
   const double omega = g.omega;
 
   // Per-position set-up: in-plane offset (clamped) and masks.
   int off[kK3];
-  unsigned valid = 0, ring = 0, core = 0, par = 0;
+  unsigned valid = 0, core = 0, par = 0, act[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) act[k] = 0;
 #pragma unroll
   for (int k = 0; k < kK3; ++k) {
     const int p = tid + kT3 * k;
     off[k] = 0;
     if (p < P) {
       const int ry = p / RX, rx = p - ry * RX;
-      const int x = x0 - 2 + rx, y = y0 - 2 + ry;
+      const int x = x0 - S + rx, y = y0 - S + ry;
       const bool inter = x >= 1 && x <= n && y >= 1 && y <= n;
+      const int dist = min(min(rx, RX - 1 - rx), min(ry, RY - 1 - ry));
       off[k] = (int)(clampi(y, 0, n + 1) * g.px + clampi(x, 0, n + 1));
       valid |= 1u << k;
-      if (inter && rx >= 1 && rx <= RX - 2 && ry >= 1 && ry <= g.RY - 2) ring |= 1u << k;
-      if (inter && rx >= 2 && rx <= RX - 3 && ry >= 2 && ry <= g.RY - 3) core |= 1u << k;
+#pragma unroll
+      for (int st = 0; st < S; ++st)
+        if (inter && dist >= st + 1) act[st] |= 1u << k;
+      if (inter && dist >= S) core |= 1u << k;
       if ((x + y) & 1) par |= 1u << k;
     }
   }
 
-  double v[kW3][kK3];
-  double f[kW3][kK3];
+  double v[W][kK3];
+  double f[POIS ? W : 1][kK3];
   auto load_u = [&](double (&dst)[kK3], int z) {
     const double *b = g.A + (int64_t)clampi(z, 0, n + 1) * g.plane;
 #pragma unroll
@@ -189,100 +214,98 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
     for (int k = 0; k < kK3; ++k) dst[k] = (valid >> k & 1u) ? b[off[k]] : 0.0;
   };
 
-  // Plane zr + j of step s lives in register slot (s + 1 + j) mod kW3.
-  // Before step 0 (zr = z0-1): planes z0-2 .. z0+kD3 of u, z0-1 .. z0+kD3-1 of f.
+  // Plane zbeg + j lives in register slot (1 + j) mod W, i.e. plane zr + j
+  // of step s in slot (s + 1 + j) mod W.  Before step 0: u planes
+  // j = -1 .. kD3+1, f planes j = 0 .. kD3.
 #pragma unroll
-  for (int j = -1; j <= kD3 + 1; ++j) load_u(v[(1 + j) % kW3], z0 - 1 + j);
-  if (POIS) {
+  for (int j = -1; j <= kD3 + 1; ++j) load_u(v[(1 + j) % W], zbeg + j);
+  if constexpr (POIS) {
 #pragma unroll
-    for (int j = 0; j <= kD3; ++j) load_f(f[(1 + j) % kW3], z0 - 1 + j);
+    for (int j = 0; j <= kD3; ++j) load_f(f[(1 + j) % W], zbeg + j);
   }
 
-  double dmax = 0.0;
+  double m[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) m[t] = 0.0;
   bool bad = false;
-  for (int sb = 0; sb < nsteps; sb += kW3) {
-#pragma unroll
-    for (int i = 0; i < kW3; ++i) {
+  for (int sb = 0; sb < nsteps; sb += W) {
+    static_for<0, W>([&](auto I) __attribute__((always_inline)) {
+      constexpr int i = decltype(I)::value;
       const int s = sb + i;
-      if (s >= nsteps) break;
-      const int zr = z0 - 1 + s;
-      const int c0 = (i + 1) % kW3;               // plane zr
-      const int cm1 = (i + kW3) % kW3;            // zr - 1
-      const int cm2 = (i + kW3 - 1) % kW3;        // zr - 2
-      const int cp1 = (i + 2) % kW3;              // zr + 1
-      double *Lr = L[zr % 3];
-      const double *Lb = L[(zr + 2) % 3];          // plane zr - 1
+      if (s >= nsteps) return;                   // this and the chunk's later steps
+      const int zr = zbeg + s;
+      {
+        double *Lz = L + (s % B) * PL;
+        const int c0 = (i + 1) % W;
 #pragma unroll
-      for (int k = 0; k < kK3; ++k)
-        if (valid >> k & 1u) Lr[tid + kT3 * k] = v[c0][k];
+        for (int k = 0; k < kK3; ++k)
+          if (valid >> k & 1u) Lz[tid + kT3 * k] = v[c0][k];
+      }
       __syncthreads();
-      if (zr >= 1 && zr <= n) {
+      static_for<0, S>([&](auto K) __attribute__((always_inline)) {
+        constexpr int st = decltype(K)::value;
+        const int q = zr - st;                       // this stage's plane
+        if (s >= 2 * st && q >= 1 && q <= n) {
+          constexpr int cs = ((i + 1 - st) % W + W) % W;     // plane q
+          constexpr int cd = ((i - st) % W + W) % W;         // q - 1
+          constexpr int cu = ((i + 2 - st) % W + W) % W;     // q + 1
+          double *Lq = L + ((s - st) % B) * PL;
 #pragma unroll
-        for (int k = 0; k < kK3; ++k) {
-          if ((ring >> k & 1u) && (((par >> k) + (unsigned)zr) & 1u) == 0u) {
-            const int p = tid + kT3 * k;
-            const double self = v[c0][k];
-            double sum = ((Lr[p - 1] + Lr[p + 1]) + (Lr[p - RX] + Lr[p + RX])) +
-                         (v[cm1][k] + v[cp1][k]);
-            if (POIS) sum = sum + f[c0][k];
-            const double gs = SIXTH * sum;
-            const double nu = self + omega * (gs - self);
-            v[c0][k] = nu;
-            Lr[p] = nu;
-            if (core >> k & 1u) {
-              dmax = fmax(dmax, fabs(nu - self));
+          for (int k = 0; k < kK3; ++k) {
+            if ((act[st] >> k & 1u) && (((par >> k) + (unsigned)q) & 1u) == (unsigned)(st & 1)) {
+              const int p = tid + kT3 * k;
+              const double self = v[cs][k];
+              double sum = ((Lq[p - 1] + Lq[p + 1]) + (Lq[p - RX] + Lq[p + RX])) +
+                           (v[cd][k] + v[cu][k]);
+              if constexpr (POIS) sum = sum + f[cs][k];
+              const double gs = SIXTH * sum;
+              const double nu = self + omega * (gs - self);
+              v[cs][k] = nu;
+              if constexpr (st + 1 < S) Lq[p] = nu;
+              m[st >> 1] = fmax(m[st >> 1], fabs(nu - self));
               bad = bad || !__builtin_isfinite(nu);
             }
           }
         }
-      }
-      const int zb = zr - 1;
-      if (zb >= z0) {
-#pragma unroll
-        for (int k = 0; k < kK3; ++k) {
-          if ((core >> k & 1u) && (((par >> k) + (unsigned)zb) & 1u) == 1u) {
-            const int p = tid + kT3 * k;
-            const double self = v[cm1][k];
-            double sum = ((Lb[p - 1] + Lb[p + 1]) + (Lb[p - RX] + Lb[p + RX])) +
-                         (v[cm2][k] + v[c0][k]);
-            if (POIS) sum = sum + f[cm1][k];
-            const double gs = SIXTH * sum;
-            const double nu = self + omega * (gs - self);
-            v[cm1][k] = nu;
-            dmax = fmax(dmax, fabs(nu - self));
-            bad = bad || !__builtin_isfinite(nu);
-          }
-        }
-        double *out = g.B + (int64_t)zb * g.plane;
+      });
+      // Plane zr-(S-1) has had every stage: store its core.
+      if (s >= 2 * S - 2) {
+        constexpr int cf = ((i + 2 - S) % W + W) % W;
+        double *out = g.B + (int64_t)(zr - (S - 1)) * g.plane;
 #pragma unroll
         for (int k = 0; k < kK3; ++k)
-          if (core >> k & 1u) out[off[k]] = v[cm1][k];
+          if (core >> k & 1u) out[off[k]] = v[cf][k];
       }
-      // Plane zr-2 of u is dead: its slot takes plane zr+kD3+2.  f's planes
-      // zr-1 .. zr+kD3 stay live; f plane zr+kD3+1 takes the free slot.
-      if (zr + kD3 + 2 <= z1 + 1) load_u(v[cm2], zr + kD3 + 2);
-      if (POIS && zr + kD3 + 1 <= z1) load_f(f[(i + kD3 + 2) % kW3], zr + kD3 + 1);
-    }
+      // u plane zr-S is dead: its slot takes plane zr+kD3+2.  f planes
+      // zr-(S-2) .. zr+kD3 stay live; f plane zr+kD3+1 takes a free slot.
+      if (zr + kD3 + 2 <= zlast) load_u(v[(i + kD3 + 3) % W], zr + kD3 + 2);
+      if constexpr (POIS)
+        if (zr + kD3 + 1 <= zlast - 1) load_f(f[(i + kD3 + 2) % W], zr + kD3 + 1);
+    });
   }
 
-  // Workgroup maximum, one report per workgroup from its first wave.
+  // Workgroup maxima, one report per workgroup from its first wave.
   const int wave = tid / 64, lane = tid % 64;
-  const double wm = wave_max(dmax);
   const bool wb = __ballot(bad) != 0;
-  if (lane == 0) {
-    wmax[wave] = wm;
-    wbad[wave] = wb;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const double wm = wave_max(m[t]);
+    if (lane == 0) wmax[wave][t] = wm;
   }
+  if (lane == 0) wbad[wave] = wb;
   __syncthreads();
   if (wave != 0) return;
-  double mx[1] = {0.0};
+  double mx[T];
   bool bb = false;
 #pragma unroll
+  for (int t = 0; t < T; ++t) mx[t] = 0.0;
+#pragma unroll
   for (int w = 0; w < kT3 / 64; ++w) {
-    mx[0] = fmax(mx[0], wmax[w]);
+#pragma unroll
+    for (int t = 0; t < T; ++t) mx[t] = fmax(mx[t], wmax[w][t]);
     bb = bb || wbad[w];
   }
-  report_pass<1>(ctl, sc, mx, 1, bb && lane == 0, (int)(blockIdx.x % kSlots), gridDim.x);
+  report_pass<T>(ctl, sc, mx, T, bb && lane == 0, (int)(blockIdx.x % kSlots), gridDim.x);
 }
 
 // Pack u (n^3), the six faces (6 n^2) and h*h*f into the padded grid; every
@@ -344,20 +367,21 @@ hipError_t launch_unpack3d(const double *U, double *u, int n, hipStream_t s) {
 // for coalesced rows, or the whole side) and the tallest equal y-bands that
 // fit, the x-y shape with the fewest region positions per core cell; then the
 // z-range length (at least 4 planes) minimising (rounds of resident
-// workgroups) x (planes a tile walks, Zs + 4, plus about 2 planes of
+// workgroups) x (planes a tile walks, Zs + 2S, plus about 2 planes of
 // start-up), so that the tiles fill whole rounds without long walks.
-Tiling3 tiling3(int n, int cx, int cy, int zs, int slots) {
+Tiling3 tiling3(int n, int T, int cx, int cy, int zs, int slots) {
   Tiling3 t{};
+  const int ring = 2 * T, PL = stream3d_positions(T);
   auto shape = [&](int ntx) {
     Tiling3 r{};
     r.ntx = ntx;
     r.CX = (n + ntx - 1) / ntx;
-    r.RX = r.CX + 4;
-    int cyw = cy > 0 ? cy : std::min(kP3 / r.RX, n + 4) - 4;
+    r.RX = r.CX + 2 * ring;
+    int cyw = cy > 0 ? cy : std::min(PL / r.RX, n + 2 * ring) - 2 * ring;
     cyw = std::max(1, std::min(cyw, n));
     r.nty = (n + cyw - 1) / cyw;
     r.CY = (n + r.nty - 1) / r.nty;
-    r.RY = r.CY + 4;
+    r.RY = r.CY + 2 * ring;
     return r;
   };
   if (cx > 0) {
@@ -366,9 +390,9 @@ Tiling3 tiling3(int n, int cx, int cy, int zs, int slots) {
     double best = 1e30;
     for (int ntx = 1; ntx <= n; ++ntx) {
       const Tiling3 r = shape(ntx);
-      if (r.RX * 5 > kP3) continue;
+      if (r.RX * (1 + 2 * ring) > PL) continue;
       if (r.RX < 32 && ntx > 1) break;                 // narrower strips only shrink
-      if (r.RX * r.RY > kP3) continue;
+      if (r.RX * r.RY > PL) continue;
       const double cost = (double)r.RX * r.RY / ((double)r.CX * r.CY);
       if (cost < best - 1e-9) {
         best = cost;
@@ -385,10 +409,10 @@ Tiling3 tiling3(int n, int cx, int cy, int zs, int slots) {
     for (int nzt = 1; nzt <= n; ++nzt) {
       const int Zs = (n + nzt - 1) / nzt;
       if (nzt > 1 && (n + Zs - 1) / Zs != nzt) continue;   // same Zs as a smaller count
-      if (Zs < std::min(n, 4)) continue;                   // walks of 1-3 planes load 5-7
+      if (Zs < std::min(n, 4)) continue;                   // walks of 1-3 planes load many
       const long long tiles = (long long)nxy * nzt;
       const long long rounds = (tiles + std::max(slots, 1) - 1) / std::max(slots, 1);
-      const double cost = (double)rounds * (Zs + 6);
+      const double cost = (double)rounds * (Zs + 2 * ring + 2);
       if (cost < best - 1e-9) {
         best = cost;
         zsw = Zs;
@@ -398,16 +422,20 @@ Tiling3 tiling3(int n, int cx, int cy, int zs, int slots) {
   zsw = std::max(1, std::min(zsw, n));
   t.nzt = (n + zsw - 1) / zsw;
   t.Zs = (n + t.nzt - 1) / t.nzt;
-  t.ok = t.RX * t.RY <= kP3;
+  t.T = T;
+  t.ok = t.RX * t.RY <= PL;
   return t;
 }
 
-int stream3d_blocks_per_cu(bool pois) {
+int stream3d_blocks_per_cu(int T, bool pois) {
   int b = 0;
-  hipError_t e = pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &b, sor3d_stream_kernel<true>, kT3, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                            &b, sor3d_stream_kernel<false>, kT3, 0);
+  hipError_t e;
+  if (T == 1)
+    e = pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, sor3d_stream_kernel<1, true>, kT3, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, sor3d_stream_kernel<1, false>, kT3, 0);
+  else
+    e = pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, sor3d_stream_kernel<2, true>, kT3, 0)
+             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, sor3d_stream_kernel<2, false>, kT3, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -416,16 +444,21 @@ int stream3d_blocks_per_cu(bool pois) {
 }
 
 hipError_t launch_sor3d_stream(const double *A, double *B, const double *F, int n,
-                               double omega, const Tiling3 &t, Ctl *ctl, const Sched &sc,
-                               hipStream_t s) {
+                               double omega, const Tiling3 &t, int T, Ctl *ctl,
+                               const Sched &sc, hipStream_t s) {
+  if (T != 1 && T != 2) return hipErrorInvalidValue;
   const int64_t px = grid3_pitch(n);
   const Geo3 g{A, B, F, px, px * (int64_t)(n + 2), n, t.RX, t.RY, t.CX, t.CY, t.Zs,
                t.ntx, t.nty, omega};
   const unsigned blocks = (unsigned)(t.ntx * t.nty * t.nzt);
-  if (F)
-    hipLaunchKernelGGL(sor3d_stream_kernel<true>, dim3(blocks), dim3(kT3), 0, s, g, ctl, sc);
-  else
-    hipLaunchKernelGGL(sor3d_stream_kernel<false>, dim3(blocks), dim3(kT3), 0, s, g, ctl, sc);
+  const dim3 grid(blocks), block(kT3);
+  if (T == 1) {
+    if (F) hipLaunchKernelGGL((sor3d_stream_kernel<1, true>), grid, block, 0, s, g, ctl, sc);
+    else hipLaunchKernelGGL((sor3d_stream_kernel<1, false>), grid, block, 0, s, g, ctl, sc);
+  } else {
+    if (F) hipLaunchKernelGGL((sor3d_stream_kernel<2, true>), grid, block, 0, s, g, ctl, sc);
+    else hipLaunchKernelGGL((sor3d_stream_kernel<2, false>), grid, block, 0, s, g, ctl, sc);
+  }
   return hipGetLastError();
 }
 

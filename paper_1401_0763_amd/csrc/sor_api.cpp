@@ -265,40 +265,53 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   }
 }
 
-// Tiling of a 3-D solve of side n with the streaming kernel: the context's
-// overrides, the rest chosen so the tiles fill the resident workgroups.
-Tiling3 tiling3_for(sor_ctx *c, int n, bool pois) {
+// Iterations per launch of a 3-D streaming solve: 2 when every check falls at
+// the end of a two-iteration pass (check_every even; an odd max_iters ends
+// with a one-iteration pass), else 1; a context setting of 1 or 2 is
+// honoured under the same condition.
+int iters3d_for(sor_ctx *c, int64_t check_every) {
+  const int want = c->tiling3d[0] > 0 ? c->tiling3d[0] : 2;
+  return (want == 2 && check_every % 2 == 0) ? 2 : 1;
+}
+
+// Tiling of a 3-D solve of side n with T iterations per launch: the
+// context's overrides, the rest chosen so the tiles fill the resident
+// workgroups.
+Tiling3 tiling3_for(sor_ctx *c, int n, bool pois, int T) {
   if (c->cus == 0) {
     hipDeviceProp_t prop;
     c->cus = hipGetDeviceProperties(&prop, c->device) == hipSuccess ? prop.multiProcessorCount
                                                                     : 256;
     (void)hipGetLastError();
   }
-  int &occ = c->occ3[pois ? 1 : 0];
-  if (occ == 0) occ = std::max(1, stream3d_blocks_per_cu(pois));
-  return tiling3(n, c->tiling3d[0], c->tiling3d[1], c->tiling3d[2], occ * c->cus);
+  int &occ = c->occ3[T - 1][pois ? 1 : 0];
+  if (occ == 0) occ = std::max(1, stream3d_blocks_per_cu(T, pois));
+  return tiling3(n, T, c->tiling3d[1], c->tiling3d[2], c->tiling3d[3], occ * c->cus);
 }
 
-// Solves whose every pass is one iteration (the 3-D kernels, the Jacobi and
-// four-colour orderings): iterations in chunks of 1, 2, 4 ... 64, the device
-// verdict read back after each chunk (the 2-D loop with one-iteration passes
-// and no re-run, since a pass never overshoots).  launch(k) enqueues
-// iteration k (0-based) on s.  Launches after a stop exit at once, so a
-// ping-pong solve's result is in its first grid after an even number of
-// executed passes (res->passes), else in its second.
+// Solves whose passes never overshoot a check (the 3-D kernels, the Jacobi
+// and four-colour orderings): passes in chunks of 1, 2, 4 ... 64 launches,
+// the device verdict read back after each chunk (the 2-D loop without its
+// re-run).  launch(done, pass, iters) enqueues the pass that starts after
+// `done` iterations (0-based pass number `pass`) on s and sets iters to the
+// iterations it applies.  Launches after a stop exit at once, so a ping-pong
+// solve's result is in its first grid after an even number of executed
+// passes (res->passes), else in its second.
 template <class Launch>
 sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_result *res,
                               double *hist, Launch launch) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
-  long long done = 0, chunk = 1;
+  long long done = 0, chunk = 1, npass = 0;
   res->converged = 0;
   res->iterations = sc.max_iters;
   res->final_max_delta = NAN;
   res->passes = 0;
+  std::vector<long long> pass_end;        // iteration at the end of each pass of a chunk
   for (;;) {
     const long long chunk_it0 = done;
     long long k = 0;
+    pass_end.clear();
     for (; k < chunk && done < sc.max_iters; ++k) {
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (c->prof) {
@@ -306,10 +319,13 @@ sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_re
         if (pst != SOR_OK) return pst;
         HIP_TRY(c, hipEventRecord(e0, s));
       }
-      HIP_TRY(c, launch(done));
+      int iters = 1;
+      HIP_TRY(c, launch(done, npass, iters));
       if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
-      done += 1;
-      if (done - chunk_it0 >= kHistCap - 1) { ++k; break; }
+      done += iters;
+      npass += 1;
+      pass_end.push_back(done);
+      if (done - chunk_it0 >= kHistCap - 2) { ++k; break; }
     }
     HIP_TRY(c, hipMemcpyAsync(c->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -318,7 +334,7 @@ sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_re
     res->passes = h.passes_done;
     if (c->prof) {
       for (long long j = 0; j < k; ++j) {
-        if (h.stop && chunk_it0 + j >= h.stop_iter) break;    // exited early
+        if (h.stop && (j == 0 ? chunk_it0 : pass_end[j - 1]) >= h.stop_iter) break;   // exited early
         float ms = 0.f;
         HIP_TRY(c, hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]));
         c->prof_ms += ms;
@@ -345,17 +361,23 @@ sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_re
   }
 }
 
-// 3-D solve: the streaming kernel alternates A -> B and B -> A; the colour
-// kernel (t == nullptr) works in place on A.
+// 3-D solve: the streaming kernel alternates A -> B and B -> A (T iterations
+// per pass, a one-iteration pass for an odd remainder); the colour kernel
+// (t == nullptr) works in place on A, one iteration per pass.
 sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, int n,
-                            double omega, const Tiling3 *t, const Sched &sc,
-                            hipStream_t s, sor_result *res, double *hist,
+                            double omega, const Tiling3 *t, const Tiling3 *t1,
+                            const Sched &sc, hipStream_t s, sor_result *res, double *hist,
                             double **result_grid) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
-  const sor_status st = run_iteration_loop(c, sc, s, res, hist, [&](long long k) {
+  const sor_status st = run_iteration_loop(c, sc, s, res, hist,
+                                           [&](long long done, long long pass, int &iters) {
+    iters = 1;
     if (!t) return launch_sor3d_iteration(A, F, n, omega, ctl, sc, s);
-    const bool even = (k & 1) == 0;
-    return launch_sor3d_stream(even ? A : B, even ? B : A, F, n, omega, *t, ctl, sc, s);
+    const bool even = (pass & 1) == 0;
+    const bool two = t->T == 2 && sc.max_iters - done >= 2;
+    iters = two ? 2 : 1;
+    return launch_sor3d_stream(even ? A : B, even ? B : A, F, n, omega, two ? *t : *t1,
+                               iters, ctl, sc, s);
   });
   *result_grid = (t && (res->passes & 1)) ? B : A;
   return st;
@@ -540,12 +562,14 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
   if ((st = check_sched(c, tol, max_iters, check_every)) != SOR_OK) return st;
   hipStream_t s = (hipStream_t)stream;
   const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
-  Tiling3 t{};
+  Tiling3 t{}, t1{};
   if (!simple) {
-    t = tiling3_for(c, n, rhs != nullptr);
-    if (!t.ok)
+    const int T = iters3d_for(c, check_every);
+    t = tiling3_for(c, n, rhs != nullptr, T);
+    t1 = T == 1 ? t : tiling3_for(c, n, rhs != nullptr, 1);
+    if (!t.ok || !t1.ok)
       return fail(c, SOR_EINVAL, "3-D tile region %d x %d exceeds one workgroup's positions",
-                  t.RX, t.RY);
+                  t.ok ? t1.RX : t.RX, t.ok ? t1.RY : t.RY);
   }
   const size_t elems = (size_t)grid3_pitch(n) * (size_t)(n + 2) * (size_t)(n + 2);
   if ((st = ensure(c, kGridA64, elems * sizeof(double)))) return st;
@@ -560,7 +584,7 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
   out->rel_residual = NAN;
   const Sched sc{max_iters, check_every, tol};
   double *res_grid = A;
-  st = run_iterations3d(c, A, B, F, n, omega, simple ? nullptr : &t, sc, s, out, hist,
+  st = run_iterations3d(c, A, B, F, n, omega, simple ? nullptr : &t, &t1, sc, s, out, hist,
                         &res_grid);
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack3d(res_grid, u, n, s));
@@ -599,7 +623,8 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
   *out = sor_result{};
   out->rel_residual = NAN;
   const Sched sc{max_iters, check_every, tol};
-  st = run_iteration_loop(c, sc, s, out, hist, [&](long long k) {
+  st = run_iteration_loop(c, sc, s, out, hist, [&](long long, long long k, int &iters) {
+    iters = 1;
     if (!jacobi) return launch_colour4_iteration(A, F, L.pitch, n, omega, ctl, sc, s);
     const bool even = (k & 1) == 0;
     return launch_jacobi_iteration(even ? A : B, even ? B : A, F, L.pitch, n, omega, ctl, sc,
@@ -613,28 +638,39 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
   return st;
 }
 
-sor_status sor_ctx_set_tiling3d(sor_ctx *c, int32_t cx, int32_t cy, int32_t zs) {
+sor_status sor_ctx_set_tiling3d(sor_ctx *c, int32_t iters_per_launch, int32_t cx, int32_t cy,
+                                int32_t zs) {
   if (!c) return SOR_EINVAL;
   c->err.clear();
+  if (iters_per_launch < 0 || iters_per_launch > 2)
+    return fail(c, SOR_EINVAL, "3-D tiling: iters_per_launch = %d not in 0..2", iters_per_launch);
   if (cx < 0 || cy < 0 || zs < 0)
     return fail(c, SOR_EINVAL, "3-D tiling (%d, %d, %d): sizes must be >= 0", cx, cy, zs);
-  if (cx > 0 && (cx + 4) * 5 > 2048)
+  const int ring = iters_per_launch == 2 ? 4 : 2;
+  const int PL = stream3d_positions(iters_per_launch == 2 ? 2 : 1);
+  if (cx > 0 && (cx + 2 * ring) * (1 + 2 * ring) > PL)
     return fail(c, SOR_EINVAL, "3-D tiling: cx = %d leaves no room for a row of tiles", cx);
-  if (cx > 0 && cy > 0 && (cx + 4) * (cy + 4) > 2048)
-    return fail(c, SOR_EINVAL, "3-D tiling: (%d + 4) x (%d + 4) positions exceed 2048", cx, cy);
-  c->tiling3d[0] = cx;
-  c->tiling3d[1] = cy;
-  c->tiling3d[2] = zs;
+  if (cx > 0 && cy > 0 && (cx + 2 * ring) * (cy + 2 * ring) > PL)
+    return fail(c, SOR_EINVAL, "3-D tiling: (%d + %d) x (%d + %d) positions exceed %d", cx,
+                2 * ring, cy, 2 * ring, PL);
+  c->tiling3d[0] = iters_per_launch;
+  c->tiling3d[1] = cx;
+  c->tiling3d[2] = cy;
+  c->tiling3d[3] = zs;
   return SOR_OK;
 }
 
-sor_status sor_ctx_tiling3d_for(sor_ctx *c, int32_t n, int32_t has_rhs, int32_t *cx,
-                                int32_t *cy, int32_t *zs) {
-  if (!c || !cx || !cy || !zs) return SOR_EINVAL;
+sor_status sor_ctx_tiling3d_for(sor_ctx *c, int32_t n, int32_t has_rhs, int64_t check_every,
+                                int32_t *iters_per_launch, int32_t *cx, int32_t *cy,
+                                int32_t *zs) {
+  if (!c || !iters_per_launch || !cx || !cy || !zs) return SOR_EINVAL;
   c->err.clear();
   if (n < 1 || n > kMaxN3) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN3);
+  if (check_every < 1) return fail(c, SOR_EINVAL, "check_every must be >= 1");
   HIP_TRY(c, hipSetDevice(c->device));
-  const Tiling3 t = tiling3_for(c, n, has_rhs != 0);
+  const int T = iters3d_for(c, check_every);
+  const Tiling3 t = tiling3_for(c, n, has_rhs != 0, T);
+  *iters_per_launch = T;
   *cx = t.CX;
   *cy = t.CY;
   *zs = t.Zs;

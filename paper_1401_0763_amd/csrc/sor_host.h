@@ -45,8 +45,8 @@ struct sor_ctx {
   sor::BatchState *batch = nullptr;                    // batched-solve state
   int cus = 0;                                         // compute units (lazy)
   int occ[3][7][2] = {};                               // pass blocks per CU (lazy)
-  int tiling3d[3] = {0, 0, 0};                         // 3-D core cx, cy, zs; 0: auto
-  int occ3[2] = {};                                    // 3-D stream blocks per CU (lazy)
+  int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
+  int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)
 };
 
 namespace sor {

@@ -56,9 +56,14 @@ def run3(sor, ctx, g, tol, iters, K, hist=True):
     return res, u.cpu().numpy()
 
 
-# Streaming-kernel tilings (core cx, cy, zs; 0 = automatic): ragged strips,
-# bands and z-ranges, one-plane ranges, the widest strips.
-TILINGS3 = [(0, 0, 0), (3, 2, 2), (4, 3, 3), (7, 5, 1), (124, 0, 0), (30, 11, 5), (0, 0, 64)]
+# Streaming-kernel set-ups (iterations per launch, core cx, cy, zs; 0 =
+# automatic): ragged strips, bands and z-ranges, one-plane ranges, the widest
+# strips, one and two iterations per launch.  Two iterations per launch need
+# an even check_every; the odd iteration counts below end with a
+# one-iteration launch.
+TILINGS3 = [(0, 0, 0, 0), (1, 3, 2, 2), (2, 3, 2, 2), (1, 4, 3, 3), (2, 4, 3, 3),
+            (1, 7, 5, 1), (2, 9, 4, 1), (1, 124, 0, 0), (2, 120, 0, 0), (2, 30, 11, 5),
+            (1, 0, 0, 64), (2, 0, 0, 64)]
 
 
 @pytest.mark.parametrize("n,with_f,iters", [
@@ -67,13 +72,14 @@ TILINGS3 = [(0, 0, 0), (3, 2, 2), (4, 3, 3), (7, 5, 1), (124, 0, 0), (30, 11, 5)
 def test_fixed_iterations_bitwise(sor, ctx, n, with_f, iters):
     g = random_cube(300 + n, n, with_f=with_f, nonzero_u0=True)
     ref = oracle.sor3d_f64(g.u0, g.bdy, g.f, g.omega, 0.0, iters, 1, threads=8, hist=True)
-    for cx, cy, zs in TILINGS3:
-        _say(f"3d stream n={n} f={with_f} iters={iters} tiling=({cx},{cy},{zs})")
-        ctx.set_tiling3d(cx, cy, zs)
-        res, u = run3(sor, ctx, g, 0.0, iters, 1)
+    for T, cx, cy, zs in TILINGS3:
+        K = 2 if T != 1 else 1        # tol 0: the check cadence changes nothing else
+        _say(f"3d stream n={n} f={with_f} iters={iters} T={T} tiling=({cx},{cy},{zs})")
+        ctx.set_tiling3d(cx, cy, zs, iters=T)
+        res, u = run3(sor, ctx, g, 0.0, iters, K)
         assert res.status == sor.NOT_CONVERGED and res.iterations == iters
-        assert_bitwise(u, ref.u, f"u n={n} tiling=({cx},{cy},{zs})")
-        assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} tiling=({cx},{cy},{zs})")
+        assert_bitwise(u, ref.u, f"u n={n} T={T} tiling=({cx},{cy},{zs})")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"hist n={n} T={T} tiling=({cx},{cy},{zs})")
     _say(f"3d colour kernel n={n}")
     ctx.set_tiling3d(0, 0, 0)
     ctx.set_kernel(sor.KERNEL_SIMPLE)
@@ -92,7 +98,7 @@ def test_omega_values_bitwise(sor, ctx, omega):
     assert_bitwise(np.array(res.hist), ref.mhist, f"hist omega={omega}")
 
 
-@pytest.mark.parametrize("K", [1, 5, 10])
+@pytest.mark.parametrize("K", [1, 2, 5, 10])
 def test_to_tolerance_same_stop(sor, ctx, K):
     """Converges; stops at the same checked iteration with the same change
     and the same grid (the chunked host loop never overshoots the stop, and
@@ -128,23 +134,30 @@ def test_sampled_cells_at_256_against_converged_oracle(sor, ctx):
     on both sides and compare the full grid (the oracle at 8 threads)."""
     n = 256
     g = random_cube(9, n, with_f=False)
-    iters = 20
+    iters = 21
     _say("3d n=256 oracle")
     ref = oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, 0.0, iters, 1, threads=8, hist=True)
-    _say("3d n=256 gpu")
-    res, u = run3(sor, ctx, g, 0.0, iters, 1)
-    assert_bitwise(u, ref.u, "u n=256")
-    assert_bitwise(np.array(res.hist), ref.mhist, "hist n=256")
+    for K in (1, 10):                 # one, then two iterations per launch
+        _say(f"3d n=256 gpu K={K}")
+        res, u = run3(sor, ctx, g, 0.0, iters, K)
+        assert_bitwise(u, ref.u, f"u n=256 K={K}")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"hist n=256 K={K}")
 
 
 def test_tiling3d_reporting_and_rejection(sor, ctx):
-    cx, cy, zs = ctx.tiling3d_for(256)
-    assert (cx + 4) * (cy + 4) <= 2048 and 1 <= zs <= 256
+    T, cx, cy, zs = ctx.tiling3d_for(256)
+    assert T == 1 and (cx + 4) * (cy + 4) <= 2048 and 1 <= zs <= 256
+    T, cx, cy, zs = ctx.tiling3d_for(256, check_every=10)
+    assert T == 2 and (cx + 8) * (cy + 8) <= 2032 and 1 <= zs <= 256
     ctx.set_tiling3d(30, 11, 5)
-    assert ctx.tiling3d_for(256) == (29, 11, 5)       # 9 equal strips of <= 30
-    for bad in ((-1, 0, 0), (0, -2, 0), (0, 0, -3), (500, 0, 0), (60, 60, 0)):
+    assert ctx.tiling3d_for(256) == (1, 29, 11, 5)     # 9 equal strips of <= 30
+    assert ctx.tiling3d_for(256, check_every=4) == (2, 29, 11, 5)
+    ctx.set_tiling3d(30, 11, 5, iters=1)
+    assert ctx.tiling3d_for(256, check_every=4) == (1, 29, 11, 5)
+    for bad in ((-1, 0, 0, 0), (0, -2, 0, 0), (0, 0, -3, 0), (500, 0, 0, 0), (60, 60, 0, 0),
+                (0, 0, 0, 3), (0, 0, 0, -1), (40, 40, 0, 2)):
         with pytest.raises(sor.SorError):
-            ctx.set_tiling3d(*bad)
+            ctx.set_tiling3d(*bad[:3], iters=bad[3])
     ctx.set_tiling3d(0, 0, 0)
 
 

@@ -59,10 +59,10 @@ def test_newer_entry_points_reject_a_null_context():
                                None, None) == sor.EINVAL
     assert lib.sor_solve_variant_f64(None, 1, None, None, None, 8, 1.0, 1e-6, 10, 1,
                                      None, None, None) == sor.EINVAL
-    assert lib.sor_ctx_set_tiling3d(None, 0, 0, 0) == sor.EINVAL
-    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    assert lib.sor_ctx_tiling3d_for(None, 64, 0, ctypes.byref(a), ctypes.byref(b),
-                                    ctypes.byref(c)) == sor.EINVAL
+    assert lib.sor_ctx_set_tiling3d(None, 0, 0, 0, 0) == sor.EINVAL
+    t, a, b, c = (ctypes.c_int32() for _ in range(4))
+    assert lib.sor_ctx_tiling3d_for(None, 64, 0, 10, ctypes.byref(t), ctypes.byref(a),
+                                    ctypes.byref(b), ctypes.byref(c)) == sor.EINVAL
 
 
 def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
