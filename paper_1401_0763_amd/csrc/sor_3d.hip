@@ -102,9 +102,16 @@ __global__ __launch_bounds__(kX3 * kY3) void sor3d_colour_kernel(Grid3 g, Ctl *c
 // ---------------------------------------------------------------------------
 // Streaming kernel, T iterations (S = 2T half-sweeps) per launch.  Tile =
 // core [x0, x0+CX) x [y0, y0+CY) x [z0, z1) of interior cells; region = core
-// plus a ring of S cells in x and y (RX = CX+2S, RY = CY+2S positions), held
-// as RX*RY positions, kK3 per thread (position p = thread + kT3*k,
-// row-major).  The tile walks planes upwards: step s loads plane
+// plus a ring of S cells in x and y (RX = CX+2S by RY = CY+2S positions),
+// held as RX*RY positions in row-major order, kK3 per thread.  One
+// iteration per launch: thread t holds positions t + 256k (contiguous loads
+// and LDS accesses) and masks each half-sweep to its colour.  Two per launch
+// (twice the half-sweeps per loaded plane): RX is made odd (one more loaded
+// column when CX+2S is even), so the colour parity of position p is that of
+// p plus a tile constant; waves 0-1 hold the positions of one parity and
+// waves 2-3 the other (p = 2(t + 128k) + parity offset), and each half-sweep
+// runs on the two waves whose cells have its colour while the other two skip
+// it.  The tile walks planes upwards: step s loads plane
 // zr = z0-(S-1)+s into the pipeline and applies the S half-sweeps as stages,
 // stage k (colour k mod 2, i.e. iteration k/2's red or black phase) to plane
 // zr-k, in the order k = 0 .. S-1:
@@ -171,6 +178,12 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
   const int x0 = 1 + tx * g.CX, y0 = 1 + ty * g.CY, z0 = 1 + tz * g.Zs;
   const int z1 = min(z0 + g.Zs, n + 1);
   const int zbeg = z0 - (S - 1);                 // stage 0's first plane
+  // Position of this thread's k-th cell; with CLS, the parity class of its
+  // cells, (x + y) mod 2, is wave-uniform.
+  constexpr bool CLS = T == 2;
+  const int cls = tid >> 7, tc = tid & 127;
+  const int poff = (cls + x0 + y0) & 1;          // p = 2j + poff has (x + y) % 2 == cls
+  auto pos = [&](int k) { return CLS ? 2 * (tc + (kT3 / 2) * k) + poff : tid + kT3 * k; };
   const int nsteps = (z1 - z0) + 2 * S - 2;
   const int zlast = z1 + S - 1;                  // highest plane read
   const int P = RX * RY;
@@ -184,7 +197,7 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
   for (int k = 0; k < S; ++k) act[k] = 0;
 #pragma unroll
   for (int k = 0; k < kK3; ++k) {
-    const int p = tid + kT3 * k;
+    const int p = pos(k);
     off[k] = 0;
     if (p < P) {
       const int ry = p / RX, rx = p - ry * RX;
@@ -239,21 +252,22 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
         const int c0 = (i + 1) % W;
 #pragma unroll
         for (int k = 0; k < kK3; ++k)
-          if (valid >> k & 1u) Lz[tid + kT3 * k] = v[c0][k];
+          if (valid >> k & 1u) Lz[pos(k)] = v[c0][k];
       }
       __syncthreads();
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int st = decltype(K)::value;
         const int q = zr - st;                       // this stage's plane
-        if (s >= 2 * st && q >= 1 && q <= n) {
+        if (s >= 2 * st && q >= 1 && q <= n && (!CLS || ((cls + q) & 1) == (st & 1))) {
           constexpr int cs = ((i + 1 - st) % W + W) % W;     // plane q
           constexpr int cd = ((i - st) % W + W) % W;         // q - 1
           constexpr int cu = ((i + 2 - st) % W + W) % W;     // q + 1
           double *Lq = L + ((s - st) % B) * PL;
 #pragma unroll
           for (int k = 0; k < kK3; ++k) {
-            if ((act[st] >> k & 1u) && (((par >> k) + (unsigned)q) & 1u) == (unsigned)(st & 1)) {
-              const int p = tid + kT3 * k;
+            if ((act[st] >> k & 1u) &&
+                (CLS || (((par >> k) + (unsigned)q) & 1u) == (unsigned)(st & 1))) {
+              const int p = pos(k);
               const double self = v[cs][k];
               double sum = ((Lq[p - 1] + Lq[p + 1]) + (Lq[p - RX] + Lq[p + RX])) +
                            (v[cd][k] + v[cu][k]);
@@ -376,7 +390,7 @@ Tiling3 tiling3(int n, int T, int cx, int cy, int zs, int slots) {
     Tiling3 r{};
     r.ntx = ntx;
     r.CX = (n + ntx - 1) / ntx;
-    r.RX = r.CX + 2 * ring;
+    r.RX = r.CX + 2 * ring + ((T == 2 && !(r.CX & 1)) ? 1 : 0);   // odd for T = 2
     int cyw = cy > 0 ? cy : std::min(PL / r.RX, n + 2 * ring) - 2 * ring;
     cyw = std::max(1, std::min(cyw, n));
     r.nty = (n + cyw - 1) / cyw;

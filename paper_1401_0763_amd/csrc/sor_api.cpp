@@ -265,12 +265,13 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   }
 }
 
-// Iterations per launch of a 3-D streaming solve: 2 when every check falls at
-// the end of a two-iteration pass (check_every even; an odd max_iters ends
-// with a one-iteration pass), else 1; a context setting of 1 or 2 is
-// honoured under the same condition.
-int iters3d_for(sor_ctx *c, int64_t check_every) {
-  const int want = c->tiling3d[0] > 0 ? c->tiling3d[0] : 2;
+// Iterations per launch of a 3-D streaming solve.  Two need every check to
+// fall at the end of a two-iteration pass (check_every even; an odd max_iters
+// ends with a one-iteration pass).  By default two for Laplace problems and
+// one with a source (whose extra planes leave one wavefront per SIMD at two);
+// a context setting of 1 or 2 is honoured under the same condition.
+int iters3d_for(sor_ctx *c, int64_t check_every, bool pois) {
+  const int want = c->tiling3d[0] > 0 ? c->tiling3d[0] : (pois ? 1 : 2);
   return (want == 2 && check_every % 2 == 0) ? 2 : 1;
 }
 
@@ -564,7 +565,7 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
   const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
   Tiling3 t{}, t1{};
   if (!simple) {
-    const int T = iters3d_for(c, check_every);
+    const int T = iters3d_for(c, check_every, rhs != nullptr);
     t = tiling3_for(c, n, rhs != nullptr, T);
     t1 = T == 1 ? t : tiling3_for(c, n, rhs != nullptr, 1);
     if (!t.ok || !t1.ok)
@@ -668,7 +669,7 @@ sor_status sor_ctx_tiling3d_for(sor_ctx *c, int32_t n, int32_t has_rhs, int64_t 
   if (n < 1 || n > kMaxN3) return fail(c, SOR_EINVAL, "n = %d outside 1..%d", n, kMaxN3);
   if (check_every < 1) return fail(c, SOR_EINVAL, "check_every must be >= 1");
   HIP_TRY(c, hipSetDevice(c->device));
-  const int T = iters3d_for(c, check_every);
+  const int T = iters3d_for(c, check_every, has_rhs != 0);
   const Tiling3 t = tiling3_for(c, n, has_rhs != 0, T);
   *iters_per_launch = T;
   *cx = t.CX;
