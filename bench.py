@@ -17,13 +17,20 @@ operations per lattice update (9: three adds for the neighbour sum, the
 quarter, the difference, the relaxation product, the update, the change and
 its running maximum) over the HIP-event-timed kernel time, against the
 non-fused FP64 vector rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), with the
-HBM-equivalent bandwidth (16 algorithmic bytes per update) and the
-counter-measured traffic beside it.
+HBM-equivalent bandwidth (16 algorithmic bytes per update), the
+counter-measured traffic and the achievable bandwidth of a 1 GiB device copy
+beside it.  The CPU baseline is the oracle on up to 16 host threads, with its
+single-thread rate and the CPU model beside it.
 Under "forms" the same line reports:
   tol      the benchmark grid solved to max |du| < 1e-8 (checked every 10);
   paper    the paper's own configuration (omega 0.376, north edge 1, other
            edges 0, tol 1e-5 checked every 4000 iterations, at most 50000),
            with the iteration count the paper does not print;
+  control_8192  8192^2, 300 iterations: grids beyond the Infinity Cache;
+  3d       the 3-D extension (7-point stencil), 256^3, 1000 iterations and
+           to 1e-8, with the CPU oracle timed on 200 iterations;
+  variants the Jacobi and four-colour orderings on 4096^2 (200 iterations)
+           and iterations to 1e-8 on 128^2 beside red-black;
 and, each against plain one-grid-at-a-time FP64 on the same GPU:
   mixed    4096^2 Poisson (f = N(0,1) + 2 pi^2 sin sin, seed 3): FP64 defect
            correction around FP32 and binary16 inner sweeps vs plain FP64 SOR
@@ -82,6 +89,36 @@ def measured_traffic(n, T, seg):
 BYTES_PER_LUP_F64 = 16.0       # read u once + write u once per iteration
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Achievable HBM bandwidth: a device elementwise copy of `mib` MiB of
+    FP64 (read + write), median of `reps` event-timed runs."""
+    src = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.add(src, 0.0, out=dst)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.add(src, 0.0, out=dst)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    t = sorted(times)[len(times) // 2]
+    return round(2 * mib * (1 << 20) / t / 1e9, 1)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, iters_k, seconds):
     """Time the CPU oracle on a bounded sample of the same workload."""
     import numpy as np
@@ -98,11 +135,18 @@ def cpu_baseline(g, iters_k, seconds):
     t0 = time.perf_counter()
     oracle.sor_f64(g.u0, g.bdy, None, g.omega, 0.0, iters, iters_k, threads=threads)
     dt = time.perf_counter() - t0
+    iters1 = max(2, iters // (4 * threads))      # about a quarter as long at linear scaling
+    t0 = time.perf_counter()
+    oracle.sor_f64(g.u0, g.bdy, None, g.omega, 0.0, iters1, iters_k, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(n * n * iters / dt / 1e9, 4), "unit": "GLUP/s",
             "cores": threads, "kind": "oracle",
             "sample": f"{n}x{n} FP64 Laplace, same seeded inputs, {iters} iterations "
                       f"(check every {iters_k}), OpenMP rows-per-colour workers, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "value_1_thread": round(n * n * iters1 / dt1 / 1e9, 4),
+            "sample_1_thread": f"same grid, {iters1} iterations, {dt1:.1f} s",
+            "cpu_model": cpu_model()}
 
 
 def dst_exact(n, bdy, f):
@@ -337,7 +381,7 @@ def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
     if cpu:
         import oracle
         threads = max(1, min(len(os.sched_getaffinity(0)), 16))
-        iters_cpu = 40
+        iters_cpu = 200
         t0 = time.perf_counter()
         oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, 0.0, iters_cpu, 10, threads=threads)
         dt = time.perf_counter() - t0
@@ -404,6 +448,34 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
                                        "sample": f"same {n}^2 grid, {iters_cpu} iterations, "
                                                  f"single thread, {dt:.1f} s"}
     return out
+
+
+def form_control(sor, ctx, torch, n=8192, iters=300, K=10):
+    """8192^2 FP64 Laplace (two 537 MB grids, beyond the 256 MB Infinity
+    Cache), fixed iterations: GLUP/s with the automatic tiling."""
+    from workloads import laplace_random_boundary
+    g = laplace_random_boundary(n)
+    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    sor.solve_f64(u, b, None, g.omega, 0.0, 2 * K, K, ctx=ctx)
+    u.zero_()
+    ctx.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve_f64(u, b, None, g.omega, 0.0, iters, K, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms, launches = ctx.profile()
+    ctx.set_profiling(False)
+    T, seg = ctx.tiling_for(64, n)
+    lups = float(n) * n * r.iterations
+    return {"workload": f"laplace_random_boundary_{n}, omega_opt, {iters} iterations, "
+                        f"check every {K}",
+            "tiling": {"iters_per_pass": T, "seg_rows": seg},
+            "glups": round(lups / dt / 1e9, 1),
+            "glups_kernel": round(lups / (kern_ms * 1e-3) / 1e9, 1),
+            "avg_launch_us": round(kern_ms * 1e3 / max(launches, 1), 2),
+            "bandwidth_equiv_GBs": round(BYTES_PER_LUP_F64 * lups / (kern_ms * 1e-3) / 1e9, 1)}
 
 
 def percentile(xs, q):
@@ -495,7 +567,7 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="tol,paper,mixed,batched,3d,variants,serving",
+    ap.add_argument("--forms", default="tol,paper,control,mixed,batched,3d,variants,serving",
                     help="comma list of extra forms to measure, or 'none'")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-burst", type=int, default=80)
@@ -588,6 +660,8 @@ def main():
                      "alg_bytes_per_launch": alg_bytes},
         "bandwidth_equiv_GBs": round(glups * BYTES_PER_LUP_F64, 1),
     }
+    if not args.copy_probe_mib:
+        line["roofline"]["hbm_achievable_copy_GBs"] = copy_bandwidth(torch)
     forms = [] if args.forms == "none" else args.forms.split(",")
     line["forms"] = {}
     if "tol" in forms:
@@ -602,6 +676,9 @@ def main():
     if "batched" in forms:
         print("[bench] form: batched 512 grids", file=sys.stderr, flush=True)
         line["forms"]["batched"] = form_batched(sor, ctx, torch)
+    if "control" in forms:
+        print("[bench] form: 8192^2 control", file=sys.stderr, flush=True)
+        line["forms"]["control_8192"] = form_control(sor, ctx, torch)
     if "variants" in forms:
         print("[bench] form: Jacobi and four-colour orderings", file=sys.stderr, flush=True)
         line["forms"]["variants"] = form_variants(sor, ctx, torch,
