@@ -184,6 +184,21 @@ def test_invalid_arguments_rejected(sor, ctx):
                                ctypes.c_void_p(hb.ctypes.data), None, n, 1.5, 1e-6,
                                10, 1, None, ctypes.byref(res), None)
     assert st == sor.EINVAL
+    # empty and oversized grids are refused before anything is read
+    for bad_n in (0, -3, 65537):
+        st = ctx.lib.sor_solve_f64(ctx.handle, ctypes.c_void_p(u.data_ptr()),
+                                   ctypes.c_void_p(b.data_ptr()), None, bad_n, 1.5, 1e-6,
+                                   10, 1, None, ctypes.byref(res), None)
+        assert st == sor.EINVAL, bad_n
+        for fn in (ctx.lib.sor_solve3d_f64,):
+            assert fn(ctx.handle, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                      None, bad_n if bad_n != 65537 else 1025, 1.5, 1e-6, 10, 1, None,
+                      ctypes.byref(res), None) == sor.EINVAL, bad_n
+        for ordering in (1, 2):
+            assert ctx.lib.sor_solve_variant_f64(
+                ctx.handle, ordering, ctypes.c_void_p(u.data_ptr()),
+                ctypes.c_void_p(b.data_ptr()), None, bad_n, 1.0, 1e-6, 10, 1, None,
+                ctypes.byref(res), None) == sor.EINVAL, (ordering, bad_n)
     with pytest.raises(sor.SorError):
         ctx.set_tiling(64, 5, 64)
     with pytest.raises(sor.SorError):
