@@ -105,7 +105,7 @@ enum { SOR_KERNEL_BLOCKED = 0, SOR_KERNEL_SIMPLE = 1 };
 sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
 
 /* Tiling of the blocked kernel for one storage precision (64, 32 or 16 bits):
- * iters_per_pass in {1, 2, 3, 4, 6} (iterations applied per HBM pass) and seg_rows, the
+ * iters_per_pass in {1, 2, 3, 4, 5, 6} (iterations applied per HBM pass) and seg_rows, the
  * rows of output per wavefront (even, 8..1024).  0 in a field means "keep".
  * A new context uses iters_per_pass 6 and reports seg_rows 0: until seg_rows
  * is set, each plain solve picks it from the grid side, so that a pass has

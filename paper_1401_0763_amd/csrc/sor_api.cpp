@@ -118,7 +118,7 @@ GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *i
 // The deepest supported pass (1, 2, 3, 4 or 6 iterations) of at most
 // `left` iterations and at most T.
 int pass_depth(long long left, int T) {
-  static const int kDepths[] = {6, 4, 3, 2, 1};
+  static const int kDepths[] = {6, 5, 4, 3, 2, 1};
   for (int t : kDepths)
     if (t <= T && t <= left) return t;
   return 1;

@@ -85,7 +85,9 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
   if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, T, pois));
   const BlockGeom gm = block_geom(prec, T);
   const long long strips = (n + 1 + gm.CW - 1) / gm.CW;
-  const long long slots = (long long)occ * c->cus;
+  // Resident wavefronts, counted at most two per SIMD: passes that fit three
+  // measured faster with the taller tiles of the two-per-SIMD count.
+  const long long slots = (long long)std::min(occ, 8) * c->cus;
   const int lo = 4 * gm.S, hi = 768;
   int seg = hi;
   for (int k = 1; k <= 64; ++k) {
@@ -368,7 +370,7 @@ sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
   sor_tiling bt = tuned_tiling(c, prec, n, false);
   double best_t = INFINITY;
   hipError_t e = hipSuccess;
-  for (int T : {1, 2, 3, 4, 6}) {
+  for (int T : {1, 2, 3, 4, 5, 6}) {
     for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768}) {
       if (seg > 2 * (n + 1) && seg != 16) continue;
       GridView v;

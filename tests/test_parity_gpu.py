@@ -68,7 +68,8 @@ def assert_bitwise(a, b, what):
 # FP64, fixed iteration count, many tilings
 # ---------------------------------------------------------------------------
 
-TILINGS = [(1, 8), (2, 16), (3, 8), (4, 64), (6, 32), (6, 8), (4, 192), (6, 128)]
+TILINGS = [(1, 8), (2, 16), (3, 8), (4, 64), (5, 40), (6, 32), (6, 8), (4, 192), (5, 128),
+           (6, 128)]
 
 
 @pytest.mark.parametrize("n,with_f,iters", [
@@ -108,7 +109,7 @@ def test_f64_laplace_top_edge_to_convergence_k1(sor, ctx):
         assert_bitwise(np.array(res.hist), ref.mhist, "hist")
 
 
-@pytest.mark.parametrize("K,T", [(10, 4), (7, 3), (1, 6), (5, 6), (3, 2)])
+@pytest.mark.parametrize("K,T", [(10, 4), (7, 3), (1, 6), (5, 6), (3, 2), (4, 5), (10, 5)])
 def test_f64_check_cadence_and_rollback(sor, ctx, K, T):
     """Stops at the first checked iteration below tol, also inside a pass."""
     n = 48
@@ -200,7 +201,7 @@ def test_invalid_arguments_rejected(sor, ctx):
                 ctypes.c_void_p(b.data_ptr()), None, bad_n, 1.0, 1e-6, 10, 1, None,
                 ctypes.byref(res), None) == sor.EINVAL, (ordering, bad_n)
     with pytest.raises(sor.SorError):
-        ctx.set_tiling(64, 5, 64)
+        ctx.set_tiling(64, 7, 64)
     with pytest.raises(sor.SorError):
         ctx.set_tiling(64, 4, 7)
 
