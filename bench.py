@@ -260,16 +260,30 @@ def form_batched(sor, ctx, torch):
     timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))           # records the graph
     res, dt = timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))
     lups = sum(g.n * g.n * r.iterations for g, r in zip(grids, res))
+
+    def rel_residuals():
+        rr = []
+        for u, b, f in zip(us, bs, fs):
+            r2, b2, _ = sor.residual_f64(u, b, f, ctx=ctx)
+            rr.append(math.sqrt(r2) / math.sqrt(b2))
+        return rr
+    u64 = [u.clone() for u in us]
     out["fp64_batched"] = {"secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
                            "glups": round(lups / dt / 1e9, 1),
-                           "converged": sum(r.converged for r in res)}
+                           "converged": sum(r.converged for r in res),
+                           "max_rel_residual": float(f"{max(rel_residuals()):.3e}")}
     mspecs = [sor.MixedSpec(u, b, f, g.omega, 0.0, 1e-8, 50, 0)
               for u, b, f, g in zip(us, bs, fs, grids)]
     timed(lambda: sor.batch_solve_mixed(mspecs, 32, ctx=ctx))
     res, dt = timed(lambda: sor.batch_solve_mixed(mspecs, 32, ctx=ctx))
+    diff = max(float((u - v).abs().max()) / max(float(v.abs().max()), 1e-300)
+               for u, v in zip(us, u64))
     out["fp32_refine_batched"] = {"secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
                                   "stop": "max |correction| < 1e-8",
-                                  "converged": sum(r.converged for r in res)}
+                                  "converged": sum(r.converged for r in res),
+                                  "max_rel_residual": float(f"{max(rel_residuals()):.3e}"),
+                                  "max_rel_diff_vs_fp64_batched": float(f"{diff:.3e}")}
+    del u64
 
     def one_at_a_time():
         its = 0
