@@ -11,8 +11,8 @@
  *   every iteration updates the red cells ((i+j) even, full-array indices
  *   with the boundary at index 0) and then the black cells, each with
  *     s  = (N + S) + (W + E)   [+ h*h*f]
- *     gs = 0.25 * s                       (Gauss-Seidel value)
- *     u' = u + omega * (gs - u)           (Eq. 1 in increment form)
+ *     dg = fma(0.25, s, -u)               (Gauss-Seidel value minus u, one rounding)
+ *     u' = u + omega * dg                 (Eq. 1 in increment form)
  *   and the change of one iteration is max |u' - u| over all cells.  A check
  *   runs every check_every iterations and at the last allowed iteration; the
  *   solve stops at the first check whose change is strictly below tol.

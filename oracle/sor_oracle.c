@@ -12,8 +12,9 @@
  * header, table or helper with the GPU library and includes nothing from it.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
- * (no fused multiply-add, no reassociation: every expression below is
- * evaluated exactly in the order written, one IEEE rounding per operation).
+ * (no implicit fused multiply-add, no reassociation: every expression below
+ * is evaluated exactly in the order written, one IEEE rounding per operation;
+ * the one fused operation, fma(), is written out).
  *
  * Grid convention (the paper's red-black colouring, Sec. 3.1, Fig. 1):
  *   The n x n interior is embedded in an (n+2) x (n+2) array U with the
@@ -35,7 +36,10 @@
  *     (plus F/4 for Poisson); the sum is formed as (N + S) + (W + E), then
  *     + F, then multiplied by 0.25.
  *   - Eq. 1, X = w*Xgs + (1 - w)*Xold, is evaluated in its increment form
- *     Xold + w*(Xgs - Xold); algebraically identical, fixed here so that two
+ *     Xold + w*(Xgs - Xold), where the difference Xgs - Xold = 0.25*s - Xold is
+ *     formed with one rounding, fma(0.25, s, -Xold) (the same as rounding
+ *     0.25*s and then the difference whenever 0.25*s is a normal number);
+ *     algebraically identical, fixed here so that two
  *     implementations can agree bit for bit.
  *   - Red cells are updated first, then black cells using the new red values
  *     (Sec. 3.1).
@@ -114,8 +118,8 @@ static double orc_half_sweep_f64(int n, double *U, const double *F, double w,
             double s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
-            double gs = 0.25 * s;               /* Gauss-Seidel value */
-            double nu = old + w * (gs - old);   /* Eq. 1, increment form */
+            double dg = fma(0.25, s, -old);     /* Gauss-Seidel value - old */
+            double nu = old + w * dg;           /* Eq. 1, increment form */
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -245,8 +249,8 @@ static double orc_jacobi_sweep_f64(int n, const double *U, double *V, const doub
             double s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
-            double gs = 0.25 * s;
-            double nu = old + w * (gs - old);
+            double dg = fma(0.25, s, -old);
+            double nu = old + w * dg;
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -268,8 +272,8 @@ static double orc_colour4_sweep_f64(int n, double *U, const double *F, double w,
             double s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
-            double gs = 0.25 * s;
-            double nu = old + w * (gs - old);
+            double dg = fma(0.25, s, -old);
+            double nu = old + w * dg;
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -440,8 +444,8 @@ static float orc_half_sweep_f32(int n, float *U, const float *F, float w,
             float s = (U[AT(i - 1, j)] + U[AT(i + 1, j)]) +
                       (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
-            float gs = 0.25f * s;
-            float nu = old + w * (gs - old);
+            float dg = fmaf(0.25f, s, -old);
+            float nu = old + w * dg;
             if (half_store) nu = oracle_round_half(nu);
             float d = fabsf(nu - old);
             if (!isfinite(nu)) *bad = 1;

@@ -6,7 +6,7 @@
 // strict stopping rule on the largest change of one iteration).
 //
 // Every update is evaluated exactly as
-//   s = (N + S) + (W + E); [s = s + F]; gs = 0.25*s; u' = u + w*(gs - u)
+//   s = (N + S) + (W + E); [s = s + F]; u' = u + w*fma(0.25, s, -u)
 // with -ffp-contract=off, so an FP64 sweep reproduces the CPU definition bit
 // for bit whatever the tiling.
 #include "sor_kernels.h"
@@ -41,8 +41,8 @@ __global__ __launch_bounds__(256) void simple_colour_kernel(GridView g, Ctl *ctl
     const ct self = (ct)U[c];
     ct s = ((ct)U[c - p] + (ct)U[c + p]) + ((ct)U[c - 1] + (ct)U[c + 1]);
     if (POIS) s = s + (ct)F[c];
-    const ct gs = (ct)0.25 * s;
-    ct nu = self + (ct)g.omega * (gs - self);
+    const ct dg = vfma((ct)0.25, s, -self);
+    ct nu = self + (ct)g.omega * dg;
     if (P == kF16) nu = (ct)(st)nu;
     d = vabs(nu - self);
     bad = !__builtin_isfinite(nu);

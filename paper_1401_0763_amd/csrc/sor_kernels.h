@@ -72,6 +72,8 @@ __device__ __forceinline__ double wave_max(double x) {
 __device__ __forceinline__ float vabs(float x) { return fabsf(x); }
 __device__ __forceinline__ double vabs(double x) { return fabs(x); }
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
 
 // Spread consecutive tiles over the 8 XCDs in contiguous runs: workgroups are
@@ -383,8 +385,8 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           const ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
           ct s = (w[su][v] + w[sd][v]) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
-          const ct gs = (ct)0.25 * s;
-          ct nu = self + (omc[v] * wr[sq]) * (gs - self);
+          const ct dg = vfma((ct)0.25, s, -self);      // Gauss-Seidel value - self
+          ct nu = self + (omc[v] * wr[sq]) * dg;
           if constexpr (P == kF16) nu = (ct)(st)nu;
           const ct d = vabs(nu - self);
           w[sq][v] = nu;

@@ -1,7 +1,8 @@
 """GPU parity: the HIP path against the CPU oracle on identical seeded inputs.
 
 FP64 and FP32 plain solves must agree with the oracle bit for bit (same
-update expression, no contraction, exact max) -- both the final grid and every
+update expression and roundings, the quarter-difference fused on both sides,
+exact max) -- both the final grid and every
 iteration's max change -- and stop at the same iteration.  Mixed precision
 must agree bit for bit at a fixed number of corrections.  The residual must
 agree bit for bit per cell; its sums (different summation order) to 1e-12.
