@@ -12,7 +12,7 @@
  *   with the boundary at index 0) and then the black cells, each with
  *     s  = (N + S) + (W + E)   [+ h*h*f]
  *     dg = fma(0.25, s, -u)               (Gauss-Seidel value minus u, one rounding)
- *     u' = u + omega * dg                 (Eq. 1 in increment form)
+ *     u' = fma(omega, dg, u)              (Eq. 1 in increment form, one rounding)
  *   and the change of one iteration is max |u' - u| over all cells.  A check
  *   runs every check_every iterations and at the last allowed iteration; the
  *   solve stops at the first check whose change is strictly below tol.
@@ -172,7 +172,7 @@ sor_status sor_solve_f32(sor_ctx *ctx, float *u, const float *boundary,
  * cell (z, y, x) of the (n+2)^3 array is red when z + y + x is even, red
  * first) and stopping rule (Algorithm 1) as sor_solve_f64.  The Gauss-Seidel
  * value is (((W + E) + (N + S)) + (D + U) [+ h*h*f]) * fl(1/6), W/E, N/S and
- * D/U the x-, y- and z-neighbours, no fused multiply-add.
+ * D/U the x-, y- and z-neighbours, then u' = fma(omega, g - u, u).
  *   u         DEVICE n*n*n, index ((z-1)*n + (y-1))*n + (x-1): in initial
  *             guess, out result (caller-owned)
  *   boundary  DEVICE 6*n*n: faces x = 0 and x = n+1 (each indexed

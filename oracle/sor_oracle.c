@@ -36,8 +36,9 @@
  *     (plus F/4 for Poisson); the sum is formed as (N + S) + (W + E), then
  *     + F, then multiplied by 0.25.
  *   - Eq. 1, X = w*Xgs + (1 - w)*Xold, is evaluated in its increment form
- *     Xold + w*(Xgs - Xold), where the difference Xgs - Xold = 0.25*s - Xold is
- *     formed with one rounding, fma(0.25, s, -Xold) (the same as rounding
+ *     Xold + w*(Xgs - Xold), the product and the sum formed with one rounding,
+ *     fma(w, d, Xold), where the difference d = Xgs - Xold = 0.25*s - Xold is
+ *     also formed with one rounding, fma(0.25, s, -Xold) (the same as rounding
  *     0.25*s and then the difference whenever 0.25*s is a normal number);
  *     algebraically identical, fixed here so that two
  *     implementations can agree bit for bit.
@@ -119,7 +120,7 @@ static double orc_half_sweep_f64(int n, double *U, const double *F, double w,
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
             double dg = fma(0.25, s, -old);     /* Gauss-Seidel value - old */
-            double nu = old + w * dg;           /* Eq. 1, increment form */
+            double nu = fma(w, dg, old);        /* Eq. 1, increment form */
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -250,7 +251,7 @@ static double orc_jacobi_sweep_f64(int n, const double *U, double *V, const doub
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
             double dg = fma(0.25, s, -old);
-            double nu = old + w * dg;
+            double nu = fma(w, dg, old);
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -273,7 +274,7 @@ static double orc_colour4_sweep_f64(int n, double *U, const double *F, double w,
                        (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
             double dg = fma(0.25, s, -old);
-            double nu = old + w * dg;
+            double nu = fma(w, dg, old);
             double d = fabs(nu - old);
             if (!isfinite(nu)) *bad = 1;
             if (d > m) m = d;
@@ -445,7 +446,9 @@ static float orc_half_sweep_f32(int n, float *U, const float *F, float w,
                       (U[AT(i, j - 1)] + U[AT(i, j + 1)]);
             if (F) s = s + F[AT(i, j)];
             float dg = fmaf(0.25f, s, -old);
-            float nu = old + w * dg;
+            /* binary16 storage: the step is rounded to float (product, then
+             * sum) before the storage rounding; float storage: one rounding */
+            float nu = half_store ? old + w * dg : fmaf(w, dg, old);
             if (half_store) nu = oracle_round_half(nu);
             float d = fabsf(nu - old);
             if (!isfinite(nu)) *bad = 1;
@@ -684,7 +687,7 @@ static double orc_half_sweep3_f64(int n, double *V, const double *F, double w,
                            (V[AT3(z - 1, y, x)] + V[AT3(z + 1, y, x)]);
                 if (F) s = s + F[AT3(z, y, x)];
                 double gs = ORC_SIXTH * s;
-                double nu = old + w * (gs - old);
+                double nu = fma(w, gs - old, old);
                 double d = fabs(nu - old);
                 if (!isfinite(nu)) *bad = 1;
                 if (d > m) m = d;

@@ -3,7 +3,8 @@
 // (Sec. 2.1 Eq. 1 in increment form), colouring (Sec. 3.1 with one more
 // axis: red = z + y + x even, red first) and stopping rule (Algorithm 1) as
 // the 2-D path; the Gauss-Seidel value is ((W + E) + (N + S)) + (D + U)
-// (+ h*h*f) times fl(1/6).
+// (+ h*h*f) times fl(1/6), and the relaxation step u + w (g - u) is one fused
+// multiply-add.
 //
 // Two kernels.  The streaming kernel (default) applies one whole iteration
 // per launch from grid A into grid B: a workgroup owns a tile (an x-y patch
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(kX3 * kY3) void sor3d_colour_kernel(Grid3 g, Ctl *c
                  (g.U[c - plane] + g.U[c + plane]);
       if (POIS) s = s + g.F[c];
       const double gs = SIXTH * s;
-      const double nu = self + g.omega * (gs - self);
+      const double nu = __builtin_fma(g.omega, gs - self, self);
       dmax = fmax(dmax, fabs(nu - self));
       bad = bad || !__builtin_isfinite(nu);
       g.U[c] = nu;
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
                            (v[cd][k] + v[cu][k]);
               if constexpr (POIS) sum = sum + f[cs][k];
               const double gs = SIXTH * sum;
-              const double nu = self + omega * (gs - self);
+              const double nu = __builtin_fma(omega, gs - self, self);
               v[cs][k] = nu;
               if constexpr (st + 1 < S) Lq[p] = nu;
               m[st >> 1] = fmax(m[st >> 1], fabs(nu - self));

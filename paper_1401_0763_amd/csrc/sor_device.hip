@@ -6,7 +6,7 @@
 // strict stopping rule on the largest change of one iteration).
 //
 // Every update is evaluated exactly as
-//   s = (N + S) + (W + E); [s = s + F]; u' = u + w*fma(0.25, s, -u)
+//   s = (N + S) + (W + E); [s = s + F]; u' = fma(w, fma(0.25, s, -u), u)
 // with -ffp-contract=off, so an FP64 sweep reproduces the CPU definition bit
 // for bit whatever the tiling.
 #include "sor_kernels.h"
@@ -42,8 +42,9 @@ __global__ __launch_bounds__(256) void simple_colour_kernel(GridView g, Ctl *ctl
     ct s = ((ct)U[c - p] + (ct)U[c + p]) + ((ct)U[c - 1] + (ct)U[c + 1]);
     if (POIS) s = s + (ct)F[c];
     const ct dg = vfma((ct)0.25, s, -self);
-    ct nu = self + (ct)g.omega * dg;
-    if (P == kF16) nu = (ct)(st)nu;
+    ct nu;
+    if constexpr (P == kF16) nu = (ct)(st)(self + (ct)g.omega * dg);   // see blocked_tile
+    else nu = vfma((ct)g.omega, dg, self);
     d = vabs(nu - self);
     bad = !__builtin_isfinite(nu);
     U[c] = (st)nu;

@@ -386,7 +386,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           ct s = (w[su][v] + w[sd][v]) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
           const ct dg = vfma((ct)0.25, s, -self);      // Gauss-Seidel value - self
-          ct nu = self + (omc[v] * wr[sq]) * dg;
+          // Eq. 1 with one rounding; with binary16 storage the step is rounded
+          // to float (product, then sum) before the storage rounding, since a
+          // fused multiply-add feeding that rounding becomes one mixed-
+          // precision instruction that rounds once, straight to binary16.
+          ct nu;
+          if constexpr (P == kF16) nu = self + (omc[v] * wr[sq]) * dg;
+          else nu = vfma(omc[v] * wr[sq], dg, self);
           if constexpr (P == kF16) nu = (ct)(st)nu;
           const ct d = vabs(nu - self);
           w[sq][v] = nu;

@@ -4,8 +4,8 @@
 // and multi-colour SOR (Sec. 3.1) with four colours, colour(i, j) =
 // 2 (i mod 2) + (j mod 2) on the full array, swept in the order 0, 1, 2, 3.
 // Same Gauss-Seidel value ((N + S) + (W + E) [+ h*h*f]) * 0.25, its
-// difference from the old value formed with one rounding, increment form of
-// Eq. 1 and stopping rule (Algorithm 1) as the red-black path.
+// difference from the old value and the relaxation step each formed with one
+// rounding, increment form of Eq. 1 and stopping rule (Algorithm 1) as the red-black path.
 //
 // Both kernels walk a strip of kVR rows with one thread per column pair
 // (2t, 2t+1) of the full array, keeping the rows above, at and below the
@@ -75,7 +75,7 @@ __device__ __forceinline__ void block_report(Ctl *ctl, const Sched &sc, double d
 }
 
 __device__ __forceinline__ double relax(double self, double s, double omega) {
-  return self + omega * __builtin_fma(0.25, s, -self);
+  return __builtin_fma(omega, __builtin_fma(0.25, s, -self), self);
 }
 
 template <bool POIS>
