@@ -306,3 +306,59 @@ def test_f64_full_size_4096_fixed_iterations_bitwise(sor, ctx):
     assert res.iterations == iters
     assert_bitwise(u, ref.u, "u 4096")
     assert_bitwise(np.array(res.hist), ref.mhist, "hist 4096")
+
+
+# ---------------------------------------------------------------------------
+# Subnormal values: the fused quarter-difference and relaxation step round
+# exactly like the oracle's fma also where 0.25*s or the result is subnormal
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scale", [5e-308, 3e-309])
+def test_f64_subnormal_range_bitwise(sor, ctx, scale):
+    n = 70
+    rng = np.random.default_rng(31)
+    bdy = rng.uniform(0.0, 1.0, size=4 * n) * scale
+    u0 = rng.uniform(0.0, 1.0, size=(n, n)) * scale
+    f = rng.standard_normal((n, n)) * scale * 1e3
+    for with_f in (False, True):
+        ff = f if with_f else None
+        ref = oracle.sor_f64(u0, bdy, ff, 1.7, 0.0, 40, 1, hist=True)
+        assert np.any((ref.u != 0) & (np.abs(ref.u) < 2.2250738585072014e-308))
+        for T, seg in ((6, 32), (5, 40), (2, 16)):
+            _say(f"subnormal f64 scale={scale} f={with_f} T={T}")
+            ctx.set_tiling(64, T, seg)
+            u = dev(u0)
+            res = sor.solve_f64(u, dev(bdy), dev(ff), 1.7, 0.0, 40, 1, hist=True, ctx=ctx)
+            assert_bitwise(u.cpu().numpy(), ref.u, f"u scale={scale} T={T}")
+            assert_bitwise(np.array(res.hist), ref.mhist, f"hist scale={scale} T={T}")
+
+
+def test_f32_subnormal_range_bitwise(sor, ctx):
+    n = 70
+    rng = np.random.default_rng(32)
+    bdy = (rng.uniform(0.0, 1.0, size=4 * n) * 3e-38).astype(np.float32)
+    u0 = (rng.uniform(0.0, 1.0, size=(n, n)) * 3e-38).astype(np.float32)
+    ref = oracle.sor_f32(u0, bdy, None, 1.7, 0.0, 40, 1, hist=True)
+    assert np.any((ref.u != 0) & (np.abs(ref.u) < np.finfo(np.float32).tiny))
+    u = dev(u0, torch.float32)
+    res = sor.solve_f32(u, dev(bdy, torch.float32), None, 1.7, 0.0, 40, 1, hist=True, ctx=ctx)
+    assert_bitwise(u.cpu().numpy(), ref.u, "f32 subnormal u")
+
+
+def test_3d_and_orderings_subnormal_range_bitwise(sor, ctx):
+    n = 20
+    rng = np.random.default_rng(33)
+    faces = rng.uniform(0.0, 1.0, size=(6, n, n)) * 5e-308
+    u0 = rng.uniform(0.0, 1.0, size=(n, n, n)) * 5e-308
+    ref = oracle.sor3d_f64(u0, faces, None, 1.6, 0.0, 30, 1)
+    for K in (1, 2):
+        u = dev(u0)
+        sor.solve3d_f64(u, dev(faces), None, 1.6, 0.0, 30, K, ctx=ctx)
+        assert_bitwise(u.cpu().numpy(), ref.u, f"3-D subnormal K={K}")
+    bdy = rng.uniform(0.0, 1.0, size=4 * 50) * 5e-308
+    u2 = rng.uniform(0.0, 1.0, size=(50, 50)) * 5e-308
+    for ordering in (1, 2):
+        ref = oracle.variant_f64(ordering, u2, bdy, None, 1.3, 0.0, 25, 1)
+        u = dev(u2)
+        sor.solve_variant_f64(ordering, u, dev(bdy), None, 1.3, 0.0, 25, 1, ctx=ctx)
+        assert_bitwise(u.cpu().numpy(), ref.u, f"ordering {ordering} subnormal")
