@@ -417,11 +417,13 @@ sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *b
   BatchState *bs = nullptr;
   sor_status st = batch_state(c, &bs);
   if (st != SOR_OK) return st;
-  // A batch of G identical grids, enough for about 4096 tiles at 4
-  // iterations per pass and 64-row tiles, capped at 256 grids and 1 GiB.
+  // A batch of G identical grids, enough for about 16384 tiles at 4
+  // iterations per pass and 64-row tiles (a queue as deep as in a large
+  // mixed batch, where tile count matters less than halo per tile), capped
+  // at 256 grids and 1 GiB.
   const BlockGeom g4 = block_geom(prec, 4);
   const long long tiles = (long long)((n + 1 + g4.CW - 1) / g4.CW) * ((n + 1 + 63) / 64);
-  long long G = std::max(1LL, std::min(256LL, (4096 + tiles - 1) / tiles));
+  long long G = std::max(1LL, std::min(256LL, (16384 + tiles - 1) / tiles));
   G = std::max(1LL, std::min(G, (long long)((1ull << 30) / ((size_t)n * n * 8 * 3))));
   const size_t cells = (size_t)n * n;
   double *u = nullptr, *bdy = nullptr;
