@@ -409,7 +409,9 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
     on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
     around each iteration's launches; 16 algorithmic bytes per update against
     the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
-    128^2 grid next to red-black, all at their best omega (Jacobi: 1)."""
+    128^2 grid next to red-black, all at their best omega (Jacobi: 1).
+    Jacobi runs one iteration per launch; four-colour its blocked passes of
+    several iterations each."""
     from workloads import laplace_random_boundary
     g = laplace_random_boundary(n)
     b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
@@ -428,8 +430,9 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
         dt = time.perf_counter() - t0
         kern_ms, launches = ctx.profile()
         ctx.set_profiling(False)
-        it_us = kern_ms * 1e3 / max(launches, 1)
+        it_us = kern_ms * 1e3 / max(r.iterations, 1)
         out[name] = {"glups": round(n * n * r.iterations / dt / 1e9, 1),
+                     "launches": launches,
                      "us_per_iteration": round(it_us, 2),
                      "glups_kernel": round(n * n / (it_us * 1e-6) / 1e9, 1),
                      "hbm_equiv_GBs": round(BYTES_PER_LUP_F64 * n * n / (it_us * 1e-6) / 1e9, 1),

@@ -203,7 +203,7 @@ sor_status sor_solve3d_f64(sor_ctx *ctx, double *u, const double *boundary,
  * omega the over-relaxed Jacobi iteration).  FOUR_COLOUR is the multi-colour
  * SOR that Sec. 3.1 names, with colour(i, j) = 2 (i mod 2) + (j mod 2) on the
  * full array (boundary at index 0) and the colours swept in the order
- * 0, 1, 2, 3 (in place; colours 1 and 2 never touch, so they share a launch).
+ * 0, 1, 2, 3 (colours 1 and 2 never touch, so they are swept together).
  */
 enum {
   SOR_ORDER_RED_BLACK = 0,
@@ -215,15 +215,30 @@ enum {
  * sor_solve_f64 with the given ordering: same arguments, layout, ownership,
  * update expression ((N+S)+(W+E) [+h*h*f]) * 0.25 in increment form,
  * stopping rule (Algorithm 1), results and errors; SOR_EINVAL for an unknown
- * ordering.  JACOBI and FOUR_COLOUR run one iteration per pass (JACOBI: one
- * launch from one padded grid into a second; FOUR_COLOUR: three launches in
- * place), and ignore the context's kernel and tiling settings.
+ * ordering.  JACOBI runs one iteration per launch, from one padded grid into
+ * a second, and ignores the context's kernel and tiling settings.
+ * FOUR_COLOUR follows the context's kernel: SOR_KERNEL_BLOCKED (default)
+ * applies several iterations per HBM pass like the red-black blocked kernel
+ * (three colour sweeps per iteration instead of two half-sweeps; tiling from
+ * sor_ctx_set_variant_tiling), SOR_KERNEL_SIMPLE runs three launches per
+ * iteration in place.  Results are bit-identical either way; out->passes
+ * counts launches that did work (iterations for the simple kernel).
  */
 sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
                                  const double *boundary, const double *rhs, int32_t n,
                                  double omega, double tol, int64_t max_iters,
                                  int64_t check_every, void *stream, sor_result *out,
                                  double *max_hist);
+
+/* Tiling of the blocked four-colour kernel (ordering SOR_ORDER_FOUR_COLOUR;
+ * other orderings: SOR_EINVAL).  iters_per_pass in 1..4 (each is 3 colour
+ * sweeps, so 4 has the stage depth of red-black's 6), seg_rows even in
+ * 8..1024; 0 in a field means "keep".  A new context uses 4 and picks
+ * seg_rows from the grid side as sor_ctx_set_tiling describes.  Results do
+ * not depend on the tiling.  sor_ctx_get_variant_tiling reports the setting
+ * (seg_rows 0 until one is set). */
+sor_status sor_ctx_set_variant_tiling(sor_ctx *ctx, int32_t ordering, const sor_tiling *t);
+sor_status sor_ctx_get_variant_tiling(const sor_ctx *ctx, int32_t ordering, sor_tiling *t);
 
 /*
  * Tiling of sor_solve3d_f64's streaming kernel (not in the paper; results do

@@ -124,6 +124,10 @@ def _declare(lib):
         getattr(lib, name).restype = ctypes.c_int
     lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
     lib.sor_solve_variant_f64.restype = ctypes.c_int
+    lib.sor_ctx_set_variant_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_ctx_set_variant_tiling.restype = ctypes.c_int
+    lib.sor_ctx_get_variant_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
+    lib.sor_ctx_get_variant_tiling.restype = ctypes.c_int
     lib.sor_ctx_set_tiling3d.argtypes = [P, i32, i32, i32, i32]
     lib.sor_ctx_set_tiling3d.restype = ctypes.c_int
     pi32 = ctypes.POINTER(ctypes.c_int32)
@@ -259,6 +263,18 @@ class Context:
         t = _Tiling()
         self._check(self.lib.sor_autotune_batch(self.handle, int(bits), int(n),
                                                 ctypes.byref(t)))
+        return t.iters_per_pass, t.seg_rows
+
+    def set_variant_tiling(self, ordering: int, iters_per_pass: int = 0, seg_rows: int = 0):
+        """Tiling of the blocked four-colour kernel (0 keeps a field)."""
+        t = _Tiling(int(iters_per_pass), int(seg_rows))
+        self._check(self.lib.sor_ctx_set_variant_tiling(self.handle, int(ordering),
+                                                        ctypes.byref(t)))
+
+    def get_variant_tiling(self, ordering: int) -> tuple[int, int]:
+        t = _Tiling()
+        self._check(self.lib.sor_ctx_get_variant_tiling(self.handle, int(ordering),
+                                                        ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
 
     def get_tiling(self, bits: int) -> tuple[int, int]:

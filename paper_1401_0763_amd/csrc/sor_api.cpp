@@ -100,14 +100,14 @@ T *origin(sor_ctx *c, BufRole role, const Layout &L) {
 }
 
 GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *in,
-                   void *out, const void *F, double omega) {
+                   void *out, const void *F, double omega, int ord = 0) {
   GridView v;
   v.in = in;
   v.out = out;
   v.F = F;
   v.pitch = L.pitch;
   v.n = L.n;
-  const BlockGeom g = block_geom(prec, t.iters_per_pass);
+  const BlockGeom g = block_geom(prec, t.iters_per_pass, ord);
   v.nstrips = (L.n + 1 + g.CW - 1) / g.CW;
   v.seg_rows = t.seg_rows;
   v.nseg = (L.n + 1 + t.seg_rows - 1) / t.seg_rows;
@@ -124,9 +124,9 @@ int pass_depth(long long left, int T) {
   return 1;
 }
 
-GridView view_for(const GridView &base, int prec, int T) {
+GridView view_for(const GridView &base, int prec, int T, int ord = 0) {
   GridView v = base;
-  const BlockGeom g = block_geom(prec, T);
+  const BlockGeom g = block_geom(prec, T, ord);
   v.nstrips = (v.n + 1 + g.CW - 1) / g.CW;
   v.nseg = (v.n + 1 + v.seg_rows - 1) / v.seg_rows;
   return v;
@@ -151,19 +151,29 @@ sor_status prof_events(sor_ctx *c, size_t k, hipEvent_t *a, hipEvent_t *b) {
   return SOR_OK;
 }
 
-// Run red-black SOR sweeps on the packed grids A/B (same layout L) until the
-// stopping rule or max_iters.  On return *result_grid is the grid holding the
-// final iterate.  hist (host, may be null) receives per-iteration changes.
+// Tiling of a four-colour solve: the context's setting, with seg_rows from
+// auto_seg_rows when none was set.
+sor_tiling c4_tiling(sor_ctx *c, int n, bool pois) {
+  sor_tiling t = c->tiling_c4;
+  if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, kF64, n, t.iters_per_pass, pois, 1);
+  return t;
+}
+
+// Run SOR sweeps (red-black, or four-colour with ord 1 and FP64 grids) on the
+// packed grids A/B (same layout L) until the stopping rule or max_iters.  On
+// return *result_grid is the grid holding the final iterate.  hist (host, may
+// be null) receives per-iteration changes.
 sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       const void *F, double omega, const Sched &sc,
                       hipStream_t s, sor_result *res, double *hist,
-                      void **result_grid) {
+                      void **result_grid, int ord = 0) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
-  const sor_tiling tl = tuned_tiling(c, prec, L.n, F != nullptr);
+  const sor_tiling tl = ord ? c4_tiling(c, L.n, F != nullptr)
+                            : tuned_tiling(c, prec, L.n, F != nullptr);
   const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
   const int T = simple ? 1 : tl.iters_per_pass;
-  GridView base = make_view(L, prec, tl, A, B, F, omega);
+  GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 
   std::vector<PassRec> recs;
   long long done = 0;               // iterations enqueued
@@ -180,7 +190,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
     // Enqueue up to `chunk` passes (a truncated pass when < T iterations remain).
     for (long long k = 0; k < chunk && done < sc.max_iters; ++k) {
       const int Tp = pass_depth(sc.max_iters - done, T);
-      GridView v = simple ? base : view_for(base, prec, Tp);
+      GridView v = simple ? base : view_for(base, prec, Tp, ord);
       v.in = cur;
       v.out = simple ? cur : oth;
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -189,10 +199,13 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         if (pst != SOR_OK) return pst;
         HIP_TRY(c, hipEventRecord(e0, s));
       }
-      if (simple) {
+      if (simple && ord) {
+        HIP_TRY(c, launch_colour4_iteration((double *)cur, (const double *)F, L.pitch, L.n,
+                                            omega, ctl, sc, s));
+      } else if (simple) {
         HIP_TRY(c, launch_simple_iteration(prec, v, ctl, sc, s));
       } else {
-        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s));
+        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord));
         std::swap(cur, oth);
       }
       if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
@@ -241,10 +254,10 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         long long left = h.stop_iter - pr->it0;
         while (left > 0) {
           const int t = pass_depth(left, T);
-          GridView v = view_for(base, prec, t);
+          GridView v = view_for(base, prec, t, ord);
           v.in = src;
           v.out = dst;
-          HIP_TRY(c, launch_blocked_pass(prec, t, v, nullptr, sc, s));
+          HIP_TRY(c, launch_blocked_pass(prec, t, v, nullptr, sc, s, ord));
           ++reruns;
           *result_grid = dst;
           std::swap(src, dst);
@@ -624,19 +637,49 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
   *out = sor_result{};
   out->rel_residual = NAN;
   const Sched sc{max_iters, check_every, tol};
-  st = run_iteration_loop(c, sc, s, out, hist, [&](long long, long long k, int &iters) {
-    iters = 1;
-    if (!jacobi) return launch_colour4_iteration(A, F, L.pitch, n, omega, ctl, sc, s);
-    const bool even = (k & 1) == 0;
-    return launch_jacobi_iteration(even ? A : B, even ? B : A, F, L.pitch, n, omega, ctl, sc,
-                                   s);
-  });
-  const double *res_grid = (jacobi && (out->passes & 1)) ? B : A;
+  void *res_grid = A;
+  if (jacobi) {
+    st = run_iteration_loop(c, sc, s, out, hist, [&](long long, long long k, int &iters) {
+      iters = 1;
+      const bool even = (k & 1) == 0;
+      return launch_jacobi_iteration(even ? A : B, even ? B : A, F, L.pitch, n, omega, ctl,
+                                     sc, s);
+    });
+    res_grid = (out->passes & 1) ? B : A;
+  } else {
+    st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid, 1);
+  }
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));
     HIP_TRY(c, hipStreamSynchronize(s));
   }
   return st;
+}
+
+sor_status sor_ctx_set_variant_tiling(sor_ctx *c, int32_t ordering, const sor_tiling *t) {
+  if (!c || !t) return SOR_EINVAL;
+  c->err.clear();
+  if (ordering != SOR_ORDER_FOUR_COLOUR)
+    return fail(c, SOR_EINVAL, "ordering %d has no blocked tiling", ordering);
+  sor_tiling nt = c->tiling_c4;
+  if (t->iters_per_pass) {
+    if (!blocked_c4_T_supported(t->iters_per_pass))
+      return fail(c, SOR_EINVAL, "four-colour iters_per_pass must be in 1..%d", kTMaxC4);
+    nt.iters_per_pass = t->iters_per_pass;
+  }
+  if (t->seg_rows) {
+    if (t->seg_rows < 8 || t->seg_rows > 1024 || (t->seg_rows & 1))
+      return fail(c, SOR_EINVAL, "seg_rows must be even and in 8..1024");
+    nt.seg_rows = t->seg_rows;
+  }
+  c->tiling_c4 = nt;
+  return SOR_OK;
+}
+
+sor_status sor_ctx_get_variant_tiling(const sor_ctx *c, int32_t ordering, sor_tiling *t) {
+  if (!c || !t || ordering != SOR_ORDER_FOUR_COLOUR) return SOR_EINVAL;
+  *t = c->tiling_c4;
+  return SOR_OK;
 }
 
 sor_status sor_ctx_set_tiling3d(sor_ctx *c, int32_t iters_per_launch, int32_t cx, int32_t cy,

@@ -73,7 +73,7 @@ sor_tiling batch_tiling(sor_ctx *c, int prec, int n) {
   return t;
 }
 
-int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
+int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord) {
   if (c->cus <= 0) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
@@ -81,9 +81,9 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
       cus = 256;
     c->cus = cus;
   }
-  int &occ = c->occ[prec][T][pois ? 1 : 0];
-  if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, T, pois));
-  const BlockGeom gm = block_geom(prec, T);
+  int &occ = ord ? c->occ_c4[T][pois ? 1 : 0] : c->occ[prec][T][pois ? 1 : 0];
+  if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, T, pois, ord));
+  const BlockGeom gm = block_geom(prec, T, ord);
   const long long strips = (n + 1 + gm.CW - 1) / gm.CW;
   // Resident wavefronts, counted at most two per SIMD: passes that fit three
   // measured faster with the taller tiles of the two-per-SIMD count.
@@ -96,9 +96,9 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois) {
     if (seg <= hi) break;
   }
   seg = std::min(hi, std::max(lo, seg));
-  // A tile walks seg + 2S - 2 steps in chunks of W: round seg up so that the
+  // A tile walks seg + 2H - 2 steps in chunks of W: round seg up so that the
   // last chunk is full (fewer tiles, none of their steps wasted).
-  const int over = (seg + 2 * gm.S - 2) % gm.W;
+  const int over = (seg + 2 * gm.H - 2) % gm.W;
   if (over) seg += gm.W - over;
   return std::min(1024, seg + (seg & 1));
 }

@@ -252,13 +252,14 @@ __global__ __launch_bounds__(256) void accumulate_kernel(
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-BlockGeom block_geom(int prec, int T) {
+BlockGeom block_geom(int prec, int T, int ord) {
   BlockGeom g;
   g.V = prec_cells(prec);
-  g.S = 2 * T;
+  g.S = order_stages(ord, T);
+  g.H = order_row_halo(ord, T);
   g.A = ((g.S + g.V - 1) / g.V) * g.V;
   g.CW = kLanes * g.V - 2 * g.A;
-  g.W = blocked_window_rows(T);
+  g.W = order_window_rows(ord, T);
   return g;
 }
 
@@ -348,6 +349,14 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
 SOR_EXTERN_BLOCKED_ALL(kF64)
 SOR_EXTERN_BLOCKED_ALL(kF32)
 SOR_EXTERN_BLOCKED_ALL(kF16)
+#define SOR_EXTERN_BLOCKED_C4(T)                                               \
+  extern template hipError_t launch_blocked_PT<kF64, T, 1>(                    \
+      const GridView &, Ctl *, const Sched &, hipStream_t);                    \
+  extern template int blocked_blocks_per_cu<kF64, T, 1>(bool);
+SOR_EXTERN_BLOCKED_C4(1)
+SOR_EXTERN_BLOCKED_C4(2)
+SOR_EXTERN_BLOCKED_C4(3)
+SOR_EXTERN_BLOCKED_C4(4)
 
 template <int P>
 static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
@@ -376,7 +385,17 @@ static int blocked_blocks_per_cu_P(int T, bool pois) {
   return 0;
 }
 
-int blocked_blocks_per_cu(int prec, int T, bool pois) {
+int blocked_blocks_per_cu(int prec, int T, bool pois, int ord) {
+  if (ord) {
+    if (prec != kF64) return 0;
+    switch (T) {
+      case 1: return blocked_blocks_per_cu<kF64, 1, 1>(pois);
+      case 2: return blocked_blocks_per_cu<kF64, 2, 1>(pois);
+      case 3: return blocked_blocks_per_cu<kF64, 3, 1>(pois);
+      case 4: return blocked_blocks_per_cu<kF64, 4, 1>(pois);
+    }
+    return 0;
+  }
   switch (prec) {
     case kF64: return blocked_blocks_per_cu_P<kF64>(T, pois);
     case kF32: return blocked_blocks_per_cu_P<kF32>(T, pois);
@@ -389,8 +408,20 @@ bool blocked_T_supported(int T) {
   return T == 1 || T == 2 || T == 3 || T == 4 || T == 5 || T == 6;
 }
 
+bool blocked_c4_T_supported(int T) { return T >= 1 && T <= kTMaxC4; }
+
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, hipStream_t s) {
+                               const Sched &sc, hipStream_t s, int ord) {
+  if (ord) {
+    if (prec != kF64) return hipErrorInvalidValue;
+    switch (T) {
+      case 1: return launch_blocked_PT<kF64, 1, 1>(v, ctl, sc, s);
+      case 2: return launch_blocked_PT<kF64, 2, 1>(v, ctl, sc, s);
+      case 3: return launch_blocked_PT<kF64, 3, 1>(v, ctl, sc, s);
+      case 4: return launch_blocked_PT<kF64, 4, 1>(v, ctl, sc, s);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (prec) {
     case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s);
     case kF32: return launch_blocked_P<kF32>(T, v, ctl, sc, s);

@@ -45,6 +45,8 @@ struct sor_ctx {
   sor::BatchState *batch = nullptr;                    // batched-solve state
   int cus = 0;                                         // compute units (lazy)
   int occ[3][7][2] = {};                               // pass blocks per CU (lazy)
+  sor_tiling tiling_c4 = {4, 0};                       // four-colour passes; seg 0: by size
+  int occ_c4[sor::kTMaxC4 + 1][2] = {};                // four-colour pass blocks per CU
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
   int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)
 };
@@ -62,8 +64,9 @@ void mix_state_free(sor_ctx *c);
 // Segment rows chosen from the grid side for one plain solve: as many tiles
 // as the pass kernel has resident wavefront slots on the device (or a whole
 // multiple of that when a single round would need segments above 768 rows),
-// and at least 4*2T rows so the 2*2T halo rows stay a modest overhead.
-int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois);
+// and at least 4 times the stage count (2T red-black, 3T four-colour) so the
+// halo rows stay a modest overhead.
+int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord = 0);
 // Tiling of a plain solve of side n: the autotuned entry of its size class if
 // there is one, else the context's tiling with seg_rows from auto_seg_rows
 // when none was set.

@@ -230,12 +230,14 @@ hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, int waves,
                             hipStream_t s);
 int batch_waves_per_cu_f64();
 
-// Geometry of the blocked kernel for a precision and iterations-per-pass T.
+// Geometry of the blocked kernel for a precision, iterations-per-pass T and
+// ordering (0: red-black, 1: four-colour): V cells per lane, S stages, H halo
+// rows, A halo columns, CW core columns.
 struct BlockGeom {
-  int V, S, A, CW;
+  int V, S, H, A, CW;
   int W;        // steps per chunk of the row walk (window rows)
 };
-BlockGeom block_geom(int prec, int T);
+BlockGeom block_geom(int prec, int T, int ord = 0);
 
 // ----------------------------- launchers ----------------------------------
 hipError_t launch_ctl_reset(Ctl *ctl, hipStream_t s);
@@ -249,14 +251,17 @@ hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
                          int n, hipStream_t s);
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
-// Blocked pass of T iterations (T in 1,2,3,4,6) from v.in into v.out; the
-// view's nstrips/nseg must match T.  ctl == nullptr runs without maxima,
-// verdict or early exit.
+// Blocked pass of T iterations from v.in into v.out: red-black (ord 0, T in
+// 1..6, every precision) or four-colour (ord 1, T in 1..kTMaxC4, FP64); the
+// view's nstrips/nseg must match T and the ordering.  ctl == nullptr runs
+// without maxima, verdict or early exit.
+constexpr int kTMaxC4 = 4;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, hipStream_t s);
+                               const Sched &sc, hipStream_t s, int ord = 0);
 bool blocked_T_supported(int T);
+bool blocked_c4_T_supported(int T);
 // Pass-kernel workgroups (wavefronts) resident per CU; 0 if the query fails.
-int blocked_blocks_per_cu(int prec, int T, bool pois);
+int blocked_blocks_per_cu(int prec, int T, bool pois, int ord = 0);
 // Simple kernel: one launch per colour, in place on v.in (v.out ignored).
 hipError_t launch_simple_iteration(int prec, const GridView &v, Ctl *ctl,
                                    const Sched &sc, hipStream_t s);

@@ -223,6 +223,18 @@ __host__ __device__ constexpr int blocked_window_rows(int T) {
   return ((2 * T + SOR_PREFETCH + 2) + 1) / 2 * 2;
 }
 
+// Stage pipelines of the blocked tile by ordering: red-black applies 2
+// half-sweeps per iteration; the four-colour ordering 3 (colour 0, colours 1
+// and 2, colour 3).  The row halo is the stage count rounded up to even, so a
+// tile's first loaded row keeps the parity of its first core row.
+__host__ __device__ constexpr int order_stages(int ord, int T) { return (ord ? 3 : 2) * T; }
+__host__ __device__ constexpr int order_row_halo(int ord, int T) {
+  return (order_stages(ord, T) + 1) / 2 * 2;
+}
+__host__ __device__ constexpr int order_window_rows(int ord, int T) {
+  return ((order_stages(ord, T) + SOR_PREFETCH + 2) + 1) / 2 * 2;
+}
+
 // ---------------------------------------------------------------------------
 // Temporally blocked streaming sweep of one tile by one wavefront.
 //
@@ -264,19 +276,21 @@ __host__ __device__ constexpr int blocked_window_rows(int T) {
 // operands, as an infinity whose change is infinite, so bad is set when some
 // maximum is not finite (non-finite inputs are caught when they are packed).
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS, int COH = kCohDefault>
+template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
                                              bool &bad) {
   using st = typename PT<P>::st;
   using ct = typename PT<P>::ct;
   constexpr int V = PT<P>::V;
-  constexpr int S = 2 * T;
+  static_assert(ORD == 0 || P == kF64, "four-colour passes are instantiated for FP64");
+  constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
+  constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
   constexpr int WV = kLanes * V;
   constexpr int CW = WV - 2 * A;
   constexpr int D = SOR_PREFETCH;                // rows prefetched ahead
-  constexpr int W = blocked_window_rows(T);      // window rows (even)
+  constexpr int W = order_window_rows(ORD, T);   // window rows (even)
   constexpr int ESZ = (int)sizeof(st);
 
   const int lane = threadIdx.x & 63;
@@ -285,10 +299,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   const int seg = tile / g.nstrips;
   const int j0 = strip * CW - A;                 // first column of the strip
   const int col0 = j0 + lane * V;                // even: parity below is static
-  const int a = seg * g.seg_rows - S;            // first loaded row (even)
+  const int a = seg * g.seg_rows - H;            // first loaded row (even)
   const int core0 = seg * g.seg_rows;
   const int core1 = min(core0 + g.seg_rows, n + 1);
-  const int b = core1 + S;                       // one past the last loaded row
+  const int b = core1 + H;                       // one past the last loaded row
   const int rlo = max(core0, 1);
   const int rhi = min(core1, n + 1);
   const bool lane_core = (lane * V >= A) && (lane * V < WV - A);
@@ -353,7 +367,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   ct xs[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
-  xs[0] = lane_permute(from_hi, w[1][0]);
+  if constexpr (ORD == 0) xs[0] = lane_permute(from_hi, w[1][0]);
 
   // Steps r = a+1 .. b-2 in chunks of W, so window slots are static.
   const int nsteps = b - a - 2;
@@ -369,6 +383,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       constexpr int ve = v0 == 1 ? V - 1 : 0;
       const int to = v0 == 1 ? from_lo : from_hi;
       ct xn[S];
+      if constexpr (ORD == 0) {
       // Stage 0 of the next step updates row r+1, still at level 0 here; its
       // exchange goes first, since it is the first one used.
       xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
@@ -403,6 +418,55 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         // sink it next to its use a step later and wait for it there).
         __builtin_amdgcn_sched_barrier(0);
       });
+      } else {
+      // Four-colour ordering: stage k is colour sweep k mod 3 of iteration
+      // k/3 (colour 0 = even row and column, then colours 1 and 2 = the
+      // black cells, then colour 3 = odd row and column).  Row q = r-k has
+      // the static parity of 1+i-k; the cells a stage updates in this lane
+      // have the static parity vpar(k, q) (none for colour 0 on odd rows and
+      // colour 3 on even rows).  Stage k+1 takes the same row at the next
+      // step, so after stage k this lane sends the edge cell that stage k+1
+      // will need from it.
+      auto vpar = [](int k, int pq) constexpr {
+        const int c = k % 3;
+        return c == 0 ? (pq == 0 ? 0 : -1) : c == 1 ? ((pq + 1) & 1) : (pq == 1 ? 1 : -1);
+      };
+      {
+        constexpr int pn = i & 1;                 // parity of row r+1
+        constexpr int vn = vpar(0, pn);
+        if constexpr (vn == 0) xn[0] = lane_permute(from_lo, w[(i + 2) % W][V - 1]);
+        else if constexpr (vn == 1) xn[0] = lane_permute(from_hi, w[(i + 2) % W][0]);
+      }
+      static_for<0, S>([&](auto K) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        constexpr int sq = ((i + 1 - k) % W + W) % W;
+        constexpr int su = (sq + W - 1) % W;
+        constexpr int sd = (sq + 1) % W;
+        constexpr int pq = ((1 + i - k) % 2 + 2) % 2;
+        constexpr int vp = vpar(k, pq);
+        if constexpr (vp >= 0) {
+          static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
+            constexpr int v = vp + 2 * decltype(JV)::value;
+            const ct self = w[sq][v];
+            const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
+            const ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
+            ct s = (w[su][v] + w[sd][v]) + (left + right);
+            if constexpr (POIS) s = s + fw[sq][v];
+            const ct dg = vfma((ct)0.25, s, -self);
+            ct nu = vfma(omc[v] * wr[sq], dg, self);
+            const ct d = vabs(nu - self);
+            w[sq][v] = nu;
+            m[k / 3] = vmax(m[k / 3], d * wc[sq]);
+          });
+        }
+        if constexpr (k + 1 < S) {
+          constexpr int vq = vpar(k + 1, pq);
+          if constexpr (vq == 0) xn[k + 1] = lane_permute(from_lo, w[sq][V - 1]);
+          else if constexpr (vq == 1) xn[k + 1] = lane_permute(from_hi, w[sq][0]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      }
 #pragma unroll
       for (int k = 0; k < S; ++k) xs[k] = xn[k];
       // Row r-S+1 has had all S half-sweeps: store it if it is a core row.
@@ -426,20 +490,34 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 // One blocked pass over a whole grid: one wavefront per tile, T iterations
 // from g.in into g.out.  With a control block, the pass first exits if an
 // earlier pass met the stopping rule, then reports its maxima.
-template <int P, int T, bool POIS>
-__global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
-                                                          Sched sc) {
+template <int P, int T, bool POIS, int ORD>
+__device__ __forceinline__ void blocked_pass_body(const GridView &g, Ctl *ctl,
+                                                  const Sched &sc) {
   if (ctl && ctl_stopped(ctl)) return;
   using ct = typename PT<P>::ct;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   ct m[T];
   bool bad = false;
-  blocked_tile<P, T, POIS>(g, tile, m, bad);
+  blocked_tile<P, T, POIS, kCohDefault, ORD>(g, tile, m, bad);
   if (!ctl) return;
   double mx[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
   report_pass<T>(ctl, sc, mx, T, bad, blockIdx.x % kSlots, gridDim.x);
+}
+
+// Red-black passes.
+template <int P, int T, bool POIS>
+__global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
+                                                          Sched sc) {
+  blocked_pass_body<P, T, POIS, 0>(g, ctl, sc);
+}
+
+// Four-colour passes.
+template <int P, int T, bool POIS>
+__global__ __launch_bounds__(64) void blocked_pass_c4_kernel(GridView g, Ctl *ctl,
+                                                             Sched sc) {
+  blocked_pass_body<P, T, POIS, 1>(g, ctl, sc);
 }
 
 // Device-scope scalar loads and stores (relaxed agent-scope atomics, i.e.
@@ -538,31 +616,43 @@ __device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
   return true;
 }
 
+// The pass kernel of an ordering, as a type (for the launchers below).
+template <int P, int T, bool POIS> struct BPK {
+  static constexpr auto k = blocked_pass_kernel<P, T, POIS>;
+};
+template <int P, int T, bool POIS> struct BPK4 {
+  static constexpr auto k = blocked_pass_c4_kernel<P, T, POIS>;
+};
+
 // Host-side launch of the blocked pass for one (precision, T); each pair is
 // instantiated in its own translation unit so the unrolled bodies compile in
 // parallel.
-template <int P, int T>
+template <int P, int T, int ORD = 0>
 hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
                              hipStream_t s) {
   const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
   if (v.F)
-    hipLaunchKernelGGL((blocked_pass_kernel<P, T, true>), grid, dim3(64), 0, s,
-                       v, ctl, sc);
+    hipLaunchKernelGGL((std::conditional_t<ORD == 0, BPK<P, T, true>, BPK4<P, T, true>>::k),
+                       grid, dim3(64), 0, s, v, ctl, sc);
   else
-    hipLaunchKernelGGL((blocked_pass_kernel<P, T, false>), grid, dim3(64), 0, s,
-                       v, ctl, sc);
+    hipLaunchKernelGGL((std::conditional_t<ORD == 0, BPK<P, T, false>, BPK4<P, T, false>>::k),
+                       grid, dim3(64), 0, s, v, ctl, sc);
   return hipGetLastError();
 }
 
 // Wavefronts of the pass kernel (one per workgroup) that one CU holds at once.
-template <int P, int T>
+template <int P, int T, int ORD = 0>
 int blocked_blocks_per_cu(bool pois) {
   int nb = 0;
   const hipError_t e =
       pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(&blocked_pass_kernel<P, T, true>), 64, 0)
+                 &nb, reinterpret_cast<const void *>(
+                          std::conditional_t<ORD == 0, BPK<P, T, true>, BPK4<P, T, true>>::k),
+                 64, 0)
            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(&blocked_pass_kernel<P, T, false>), 64, 0);
+                 &nb, reinterpret_cast<const void *>(
+                          std::conditional_t<ORD == 0, BPK<P, T, false>, BPK4<P, T, false>>::k),
+                 64, 0);
   return e == hipSuccess ? nb : 0;
 }
 

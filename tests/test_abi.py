@@ -60,6 +60,11 @@ def test_newer_entry_points_reject_a_null_context():
     assert lib.sor_solve_variant_f64(None, 1, None, None, None, 8, 1.0, 1e-6, 10, 1,
                                      None, None, None) == sor.EINVAL
     assert lib.sor_ctx_set_tiling3d(None, 0, 0, 0, 0) == sor.EINVAL
+    tl = sor._Tiling(4, 64)
+    assert lib.sor_ctx_set_variant_tiling(None, sor.ORDER_FOUR_COLOUR,
+                                          ctypes.byref(tl)) == sor.EINVAL
+    assert lib.sor_ctx_get_variant_tiling(None, sor.ORDER_FOUR_COLOUR,
+                                          ctypes.byref(tl)) == sor.EINVAL
     t, a, b, c = (ctypes.c_int32() for _ in range(4))
     assert lib.sor_ctx_tiling3d_for(None, 64, 0, 10, ctypes.byref(t), ctypes.byref(a),
                                     ctypes.byref(b), ctypes.byref(c)) == sor.EINVAL

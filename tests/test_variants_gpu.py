@@ -133,3 +133,75 @@ def test_red_black_ordering_is_solve_f64_and_errors(sor, ctx):
         u = dev(g.u0)
         r = sor.solve_variant_f64(ordering, u, dev(bdy), dev(g.f), 1.0, 1e-6, 50, 1, ctx=ctx)
         assert r.status == sor.ENONFINITE, name
+
+
+# Blocked four-colour passes: depth 1..4 (truncated passes when fewer
+# iterations remain), segment heights that do and do not divide the grid, and
+# strips with a ragged last one.
+C4_TILINGS = [(1, 8), (2, 14), (3, 30), (4, 48), (4, 202), (3, 64), (2, 1024)]
+
+
+@pytest.mark.parametrize("T,seg", C4_TILINGS)
+@pytest.mark.parametrize("n,with_f,iters", [
+    (1, False, 3), (5, True, 9), (61, True, 11), (130, False, 13), (300, True, 10),
+    (513, False, 7)])
+def test_four_colour_blocked_tilings_bitwise(sor, ctx, T, seg, n, with_f, iters):
+    g = random_small(900 + n + T, n, with_f=with_f, nonzero_u0=True)
+    ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, T, seg)
+    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (T, seg)
+    _say(f"four-colour blocked T={T} seg={seg} n={n} f={with_f} iters={iters}")
+    ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, 1.37, 0.0, iters, 1, hist=True)
+    res, u = run(sor, ctx, 2, g, 1.37, 0.0, iters, 1)
+    assert res.status == sor.NOT_CONVERGED and res.iterations == iters
+    assert res.passes == -(-iters // T)     # every pass did work (no early stop)
+    assert_bitwise(u, ref.u, f"four-colour blocked u T={T} seg={seg} n={n}")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"four-colour blocked hist T={T} n={n}")
+
+
+@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("K", [1, 3, 5])
+def test_four_colour_blocked_stop_inside_a_pass(sor, ctx, T, K):
+    """Checks that fall inside a pass: the pass is redone up to the stop from
+    its intact input, so grid and change match the oracle's stop."""
+    n = 90
+    g = random_small(77 + K, n, with_f=True)
+    ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, T, 32)
+    for tol in (1e-3, 1e-7):
+        ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, g.omega, tol, 50000, K, hist=True)
+        _say(f"four-colour blocked T={T} K={K} tol={tol} ref_it={ref.iterations}")
+        assert ref.status == oracle.OK
+        res, u = run(sor, ctx, 2, g, g.omega, tol, 50000, K)
+        assert res.status == sor.OK and res.iterations == ref.iterations
+        assert res.final_max_delta == ref.final_max_delta
+        assert_bitwise(u, ref.u, f"four-colour blocked u T={T} K={K} tol={tol}")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"four-colour blocked hist T={T} K={K}")
+
+
+def test_four_colour_simple_and_blocked_agree(sor, ctx):
+    """The three-launch in-place kernel and the blocked passes give the same
+    bits (and the oracle's)."""
+    n = 257
+    g = random_small(31, n, with_f=True, nonzero_u0=True)
+    ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, g.omega, 0.0, 14, 1, hist=True)
+    ctx.set_kernel(sor.KERNEL_SIMPLE)
+    res_s, u_s = run(sor, ctx, 2, g, g.omega, 0.0, 14, 1)
+    assert res_s.passes == 14
+    ctx.set_kernel(sor.KERNEL_BLOCKED)
+    res_b, u_b = run(sor, ctx, 2, g, g.omega, 0.0, 14, 1)
+    assert res_b.passes == 4            # 4 + 4 + 4 + 2 iterations at the default depth 4
+    assert_bitwise(u_s, ref.u, "four-colour simple")
+    assert_bitwise(u_b, ref.u, "four-colour blocked")
+    assert_bitwise(np.array(res_s.hist), ref.mhist, "four-colour simple hist")
+    assert_bitwise(np.array(res_b.hist), ref.mhist, "four-colour blocked hist")
+
+
+def test_four_colour_tiling_validation(sor, ctx):
+    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 0)
+    for bad in [(5, 0), (0, 7), (0, 6), (0, 1026), (-1, 0)]:
+        with pytest.raises(sor.SorError):
+            ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, *bad)
+    for ordering in (sor.ORDER_RED_BLACK, sor.ORDER_JACOBI, 7):
+        with pytest.raises(sor.SorError):
+            ctx.set_variant_tiling(ordering, 2, 64)
+    ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, 0, 96)
+    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 96)
