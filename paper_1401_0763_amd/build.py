@@ -1,8 +1,9 @@
 """Build libsor.so for gfx950 with hipcc (in place, next to this file).
 
 Every HIP source is compiled with
-  -ffp-contract=off      no fused multiply-add: the sweep's rounding sequence is
-                         fixed (u + w*(gs - u) with separate multiply and add);
+  -ffp-contract=off      no multiply-add is fused unless the source asks for it,
+                         so every rounding of the sweep is the one written (the
+                         update's two fused steps are explicit fma calls);
   -Xclang -target-feature -Xclang -packed-fp32-ops
                          no packed FP32 instructions are generated.
 """
