@@ -297,20 +297,22 @@ def form_batched(sor, ctx, torch):
         out["fp64_batched"]["solves_per_s"] / out["fp64_one_at_a_time"]["solves_per_s"], 2)
 
     # Autotuned tiles: one batched-throughput search per half-octave size
-    # class in the batch.
+    # class in the batch, on a context of its own so that later forms keep
+    # the default tiling.
+    tctx = sor.Context(0)
     tuned = {}
     for n in sorted({g.n for g in grids}):
         c = round(2 * math.log2(n))
         if c not in tuned:
-            tuned[c] = ctx.autotune_batch(64, n)
-    timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))           # re-records the graph
-    res, dt = timed(lambda: sor.batch_solve_f64(specs, ctx=ctx))
+            tuned[c] = tctx.autotune_batch(64, n)
+    timed(lambda: sor.batch_solve_f64(specs, ctx=tctx))          # records the graph
+    res, dt = timed(lambda: sor.batch_solve_f64(specs, ctx=tctx))
     out["fp64_batched_autotuned"] = {
         "secs": round(dt, 3), "solves_per_s": round(512 / dt, 1),
         "glups": round(sum(g.n * g.n * r.iterations for g, r in zip(grids, res)) / dt / 1e9, 1),
         "converged": sum(r.converged for r in res),
         "tilings": {str(k): list(v) for k, v in sorted(tuned.items())}}
-    ctx.set_tiling(64, 6, 0)       # back to the size rule for later forms
+    tctx.close()
     return out
 
 

@@ -105,15 +105,19 @@ enum { SOR_KERNEL_BLOCKED = 0, SOR_KERNEL_SIMPLE = 1 };
 sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
 
 /* Tiling of the blocked kernel for one storage precision (64, 32 or 16 bits):
- * iters_per_pass in {1, 2, 3, 4, 5, 6} (iterations applied per HBM pass) and seg_rows, the
+ * iters_per_pass in 1..8 (iterations applied per HBM pass) and seg_rows, the
  * rows of output per wavefront (even, 8..1024).  0 in a field means "keep".
- * A new context uses iters_per_pass 6 and reports seg_rows 0: until seg_rows
- * is set, each plain solve picks it from the grid side, so that a pass has
- * about as many tiles as the device holds resident wavefronts of the pass
- * kernel (4*2*iters_per_pass..768 rows); batched solves use 64 rows below
- * n = 512, else 192 (FP64) or 96.  An autotuned entry for the grid's size
- * class (sor_autotune for plain solves, sor_autotune_batch for batched ones)
- * takes precedence. */
+ * A new context reports both as 0 (chosen per solve).  Until iters_per_pass
+ * is set, each plain solve uses 7 where the 7-deep pass kernel keeps two
+ * wavefronts resident per SIMD for the solve's precision and problem (FP64
+ * Laplace problems on gfx950), else 6; batched solves use the largest of 4,
+ * 2 and 1 not above the context's depth (6 while it is automatic).  Until seg_rows is set, each plain solve picks it from the
+ * grid side, so that a pass has about as many tiles as the device holds
+ * resident wavefronts of the pass kernel (4*2*iters_per_pass..768 rows);
+ * batched solves use 64 rows below n = 512, else 192 (FP64) or 96.  An
+ * autotuned entry for the grid's size class (sor_autotune for plain solves,
+ * sor_autotune_batch for batched ones) takes precedence.  Results do not
+ * depend on the tiling. */
 typedef struct sor_tiling {
     int32_t iters_per_pass;
     int32_t seg_rows;

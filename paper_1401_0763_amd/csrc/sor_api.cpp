@@ -115,10 +115,10 @@ GridView make_view(const Layout &L, int prec, const sor_tiling &t, const void *i
   return v;
 }
 
-// The deepest supported pass (1, 2, 3, 4 or 6 iterations) of at most
-// `left` iterations and at most T.
+// The deepest supported pass (1 to 8 iterations) of at most `left`
+// iterations and at most T.
 int pass_depth(long long left, int T) {
-  static const int kDepths[] = {6, 5, 4, 3, 2, 1};
+  static const int kDepths[] = {8, 7, 6, 5, 4, 3, 2, 1};
   for (int t : kDepths)
     if (t <= T && t <= left) return t;
   return 1;
@@ -515,7 +515,7 @@ sor_status sor_ctx_set_tiling(sor_ctx *c, int32_t bits, const sor_tiling *t) {
   sor_tiling nt = c->tiling[p];
   if (t->iters_per_pass) {
     if (!blocked_T_supported(t->iters_per_pass))
-      return fail(c, SOR_EINVAL, "iters_per_pass must be 1, 2, 3, 4 or 6");
+      return fail(c, SOR_EINVAL, "iters_per_pass must be in 1..%d", kTMax);
     nt.iters_per_pass = t->iters_per_pass;
   }
   if (t->seg_rows) {
@@ -524,6 +524,7 @@ sor_status sor_ctx_set_tiling(sor_ctx *c, int32_t bits, const sor_tiling *t) {
     nt.seg_rows = t->seg_rows;
   }
   c->tiling[p] = nt;
+  if (t->iters_per_pass) c->depth_auto[p] = false;
   clear_tuning(c, p);
   return SOR_OK;
 }
@@ -533,6 +534,7 @@ sor_status sor_ctx_get_tiling(const sor_ctx *c, int32_t bits, sor_tiling *t) {
   const int p = prec_index(bits);
   if (p < 0) return SOR_EINVAL;
   *t = c->tiling[p];
+  if (c->depth_auto[p]) t->iters_per_pass = 0;
   return SOR_OK;
 }
 

@@ -103,6 +103,12 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord) {
   return std::min(1024, seg + (seg & 1));
 }
 
+int auto_depth(sor_ctx *c, int prec, bool pois) {
+  int &occ = c->occ[prec][7][pois ? 1 : 0];
+  if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, 7, pois));
+  return occ >= 2 * 4 ? 7 : 6;      // two wavefronts on each of the CU's 4 SIMDs
+}
+
 sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {
   if (c->batch) {
     auto &m = c->batch->tune[prec];
@@ -110,6 +116,7 @@ sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {
     if (it != m.end()) return it->second;
   }
   sor_tiling t = c->tiling[prec];
+  if (c->depth_auto[prec]) t.iters_per_pass = auto_depth(c, prec, pois);
   if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, prec, n, t.iters_per_pass, pois);
   return t;
 }
@@ -370,7 +377,7 @@ sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
   sor_tiling bt = tuned_tiling(c, prec, n, false);
   double best_t = INFINITY;
   hipError_t e = hipSuccess;
-  for (int T : {1, 2, 3, 4, 5, 6}) {
+  for (int T : {1, 2, 3, 4, 5, 6, 7, 8}) {
     for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768}) {
       if (seg > 2 * (n + 1) && seg != 16) continue;
       GridView v;

@@ -1,0 +1,8 @@
+// Blocked red-black SOR pass, binary16 storage, 8 iteration(s) per pass.
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF16, 8>(const GridView &, Ctl *,
+                                              const Sched &, hipStream_t);
+template int blocked_blocks_per_cu<kF16, 8>(bool);
+}  // namespace sor

@@ -345,7 +345,8 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
   extern template int blocked_blocks_per_cu<P, T>(bool);
 #define SOR_EXTERN_BLOCKED_ALL(P)                                              \
   SOR_EXTERN_BLOCKED(P, 1) SOR_EXTERN_BLOCKED(P, 2) SOR_EXTERN_BLOCKED(P, 3)   \
-  SOR_EXTERN_BLOCKED(P, 4) SOR_EXTERN_BLOCKED(P, 5) SOR_EXTERN_BLOCKED(P, 6)
+  SOR_EXTERN_BLOCKED(P, 4) SOR_EXTERN_BLOCKED(P, 5) SOR_EXTERN_BLOCKED(P, 6)   \
+  SOR_EXTERN_BLOCKED(P, 7) SOR_EXTERN_BLOCKED(P, 8)
 SOR_EXTERN_BLOCKED_ALL(kF64)
 SOR_EXTERN_BLOCKED_ALL(kF32)
 SOR_EXTERN_BLOCKED_ALL(kF16)
@@ -368,6 +369,8 @@ static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
     case 4: return launch_blocked_PT<P, 4>(v, ctl, sc, s);
     case 5: return launch_blocked_PT<P, 5>(v, ctl, sc, s);
     case 6: return launch_blocked_PT<P, 6>(v, ctl, sc, s);
+    case 7: return launch_blocked_PT<P, 7>(v, ctl, sc, s);
+    case 8: return launch_blocked_PT<P, 8>(v, ctl, sc, s);
   }
   return hipErrorInvalidValue;
 }
@@ -381,6 +384,8 @@ static int blocked_blocks_per_cu_P(int T, bool pois) {
     case 4: return blocked_blocks_per_cu<P, 4>(pois);
     case 5: return blocked_blocks_per_cu<P, 5>(pois);
     case 6: return blocked_blocks_per_cu<P, 6>(pois);
+    case 7: return blocked_blocks_per_cu<P, 7>(pois);
+    case 8: return blocked_blocks_per_cu<P, 8>(pois);
   }
   return 0;
 }
@@ -405,7 +410,7 @@ int blocked_blocks_per_cu(int prec, int T, bool pois, int ord) {
 }
 
 bool blocked_T_supported(int T) {
-  return T == 1 || T == 2 || T == 3 || T == 4 || T == 5 || T == 6;
+  return T >= 1 && T <= kTMax;
 }
 
 bool blocked_c4_T_supported(int T) { return T >= 1 && T <= kTMaxC4; }

@@ -35,6 +35,7 @@ struct sor_ctx {
   std::string err;
   int kernel = SOR_KERNEL_BLOCKED;
   sor_tiling tiling[3] = {{6, 0}, {6, 0}, {6, 0}};  // by precision; seg 0: by size
+  bool depth_auto[3] = {true, true, true};             // depth chosen per solve until set
   sor::DevBuf bufs[sor::kNumRoles];
   sor::Ctl *host_ctl = nullptr;                        // pinned mirror
   double *host_stats = nullptr;                        // pinned [4]
@@ -44,7 +45,7 @@ struct sor_ctx {
   int64_t prof_launches = 0;
   sor::BatchState *batch = nullptr;                    // batched-solve state
   int cus = 0;                                         // compute units (lazy)
-  int occ[3][7][2] = {};                               // pass blocks per CU (lazy)
+  int occ[3][sor::kTMax + 1][2] = {};                   // pass blocks per CU (lazy)
   sor_tiling tiling_c4 = {4, 0};                       // four-colour passes; seg 0: by size
   int occ_c4[sor::kTMaxC4 + 1][2] = {};                // four-colour pass blocks per CU
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
@@ -67,9 +68,12 @@ void mix_state_free(sor_ctx *c);
 // and at least 4 times the stage count (2T red-black, 3T four-colour) so the
 // halo rows stay a modest overhead.
 int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord = 0);
+// Depth of a plain solve while the context's depth is automatic: 7 where the
+// 7-deep pass kernel keeps two wavefronts per SIMD, else 6.
+int auto_depth(sor_ctx *c, int prec, bool pois);
 // Tiling of a plain solve of side n: the autotuned entry of its size class if
-// there is one, else the context's tiling with seg_rows from auto_seg_rows
-// when none was set.
+// there is one, else the context's tiling (depth from auto_depth while it is
+// automatic) with seg_rows from auto_seg_rows when none was set.
 sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois);
 // Tiling of one grid inside a batched launch (many grids share the chip, so
 // a grid's own tile count does not need to fill it): the autotuned entry, else

@@ -252,7 +252,7 @@ hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
 // Blocked pass of T iterations from v.in into v.out: red-black (ord 0, T in
-// 1..6, every precision) or four-colour (ord 1, T in 1..kTMaxC4, FP64); the
+// 1..kTMax, every precision) or four-colour (ord 1, T in 1..kTMaxC4, FP64); the
 // view's nstrips/nseg must match T and the ordering.  ctl == nullptr runs
 // without maxima, verdict or early exit.
 constexpr int kTMaxC4 = 4;

@@ -369,6 +369,11 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
   if constexpr (ORD == 0) xs[0] = lane_permute(from_hi, w[1][0]);
 
+  // Wait here for the prologue's loads and permute.  The loop head joins
+  // this path with the loop's back edge; without the wait the compiler takes
+  // the prologue's most recent load as pending there and drains the memory
+  // queue at the head of every chunk instead of once per tile.
+  __builtin_amdgcn_s_waitcnt(0x0070);   // vmcnt(0) lgkmcnt(0)
   // Steps r = a+1 .. b-2 in chunks of W, so window slots are static.
   const int nsteps = b - a - 2;
   for (int base = 0; base < nsteps; base += W) {

@@ -125,7 +125,7 @@ def test_batch_nonfinite_grid_reported(sor, ctx):
 
 def test_autotune_returns_supported_tiling_and_keeps_results(sor, ctx):
     T, seg = ctx.autotune(64, 300)
-    assert T in (1, 2, 3, 4, 6) and 8 <= seg <= 1024
+    assert 1 <= T <= 8 and 8 <= seg <= 1024
     g = random_small(55, 300, with_f=True)
     ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 0.0, 30, 1)
     u = dev(g.u0)

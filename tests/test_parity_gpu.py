@@ -70,7 +70,7 @@ def assert_bitwise(a, b, what):
 # ---------------------------------------------------------------------------
 
 TILINGS = [(1, 8), (2, 16), (3, 8), (4, 64), (5, 40), (6, 32), (6, 8), (4, 192), (5, 128),
-           (6, 128)]
+           (6, 128), (7, 40), (7, 94), (8, 16), (8, 102)]
 
 
 @pytest.mark.parametrize("n,with_f,iters", [
@@ -110,7 +110,8 @@ def test_f64_laplace_top_edge_to_convergence_k1(sor, ctx):
         assert_bitwise(np.array(res.hist), ref.mhist, "hist")
 
 
-@pytest.mark.parametrize("K,T", [(10, 4), (7, 3), (1, 6), (5, 6), (3, 2), (4, 5), (10, 5)])
+@pytest.mark.parametrize("K,T", [(10, 4), (7, 3), (1, 6), (5, 6), (3, 2), (4, 5), (10, 5),
+                                 (10, 7), (3, 7), (10, 8), (5, 8)])
 def test_f64_check_cadence_and_rollback(sor, ctx, K, T):
     """Stops at the first checked iteration below tol, also inside a pass."""
     n = 48
@@ -202,7 +203,7 @@ def test_invalid_arguments_rejected(sor, ctx):
                 ctypes.c_void_p(b.data_ptr()), None, bad_n, 1.0, 1e-6, 10, 1, None,
                 ctypes.byref(res), None) == sor.EINVAL, (ordering, bad_n)
     with pytest.raises(sor.SorError):
-        ctx.set_tiling(64, 7, 64)
+        ctx.set_tiling(64, 9, 64)
     with pytest.raises(sor.SorError):
         ctx.set_tiling(64, 4, 7)
 
@@ -219,7 +220,7 @@ def test_f32_fixed_iterations_bitwise(sor, ctx, n, with_f):
     if g.f is not None:
         g.f = g.f.astype(np.float32).astype(np.float64)
     ref = oracle.sor_f32(g.u0, g.bdy, g.f, g.omega, 0.0, 29, 1, hist=True)
-    for T, seg in [(1, 8), (4, 64), (6, 16), (4, 96)]:
+    for T, seg in [(1, 8), (4, 64), (6, 16), (4, 96), (7, 64), (8, 32)]:
         _say(f"f32 n={n} T={T} seg={seg}")
         ctx.set_kernel(sor.KERNEL_BLOCKED)
         ctx.set_tiling(32, T, seg)
@@ -263,7 +264,7 @@ def test_mixed_fixed_outer_steps_bitwise(sor, ctx, bits, n, outer):
     g = poisson_manufactured(n, seed=40 + n)
     inner = 2 * n
     ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, outer, bits, inner)
-    for T, seg in [(4, 64), (3, 16)]:
+    for T, seg in [(4, 64), (3, 16), (8, 48)]:
         _say(f"mixed bits={bits} n={n} T={T}")
         ctx.set_kernel(sor.KERNEL_BLOCKED)
         ctx.set_tiling(bits, T, seg)
@@ -324,7 +325,7 @@ def test_f64_subnormal_range_bitwise(sor, ctx, scale):
         ff = f if with_f else None
         ref = oracle.sor_f64(u0, bdy, ff, 1.7, 0.0, 40, 1, hist=True)
         assert np.any((ref.u != 0) & (np.abs(ref.u) < 2.2250738585072014e-308))
-        for T, seg in ((6, 32), (5, 40), (2, 16)):
+        for T, seg in ((6, 32), (5, 40), (2, 16), (7, 40), (8, 32)):
             _say(f"subnormal f64 scale={scale} f={with_f} T={T}")
             ctx.set_tiling(64, T, seg)
             u = dev(u0)
@@ -362,3 +363,23 @@ def test_3d_and_orderings_subnormal_range_bitwise(sor, ctx):
         u = dev(u2)
         sor.solve_variant_f64(ordering, u, dev(bdy), None, 1.3, 0.0, 25, 1, ctx=ctx)
         assert_bitwise(u.cpu().numpy(), ref.u, f"ordering {ordering} subnormal")
+
+
+def test_automatic_depth(sor):
+    """A fresh context chooses the depth per solve (reported as 0): 7 for FP64
+    Laplace problems, whose 7-deep pass keeps two wavefronts per SIMD, and 6
+    for FP64 Poisson problems, whose 7-deep pass does not.  Setting a depth
+    ends the automatic choice."""
+    c = sor.Context(0)
+    try:
+        assert c.get_tiling(64) == (0, 0)
+        assert c.tiling_for(64, 4096)[0] == 7
+        assert c.tiling_for(64, 4096, has_rhs=True)[0] == 6
+        assert c.tiling_for(32, 4096)[0] in (6, 7)
+        c.set_tiling(64, 0, 64)
+        assert c.get_tiling(64) == (0, 64) and c.tiling_for(64, 4096) == (7, 64)
+        c.set_tiling(64, 6, 0)
+        assert c.get_tiling(64) == (6, 64) and c.tiling_for(64, 4096, True) == (6, 64)
+        assert c.tiling_for(64, 4096)[0] == 6
+    finally:
+        c.close()
