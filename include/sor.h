@@ -111,10 +111,11 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * is set, each plain solve uses 7 where the 7-deep pass kernel keeps two
  * wavefronts resident per SIMD for the solve's precision and problem (FP64
  * Laplace problems on gfx950), else 6; batched solves use the largest of 4,
- * 2 and 1 not above the context's depth (6 while it is automatic).  Until seg_rows is set, each plain solve picks it from the
- * grid side, so that a pass has about as many tiles as the device holds
- * resident wavefronts of the pass kernel (4*2*iters_per_pass..768 rows);
- * batched solves use 64 rows below n = 512, else 192 (FP64) or 96.  An
+ * 2 and 1 not above the context's depth (6 while it is automatic).  Until
+ * seg_rows is set, each plain solve picks it from the grid side, so that a
+ * pass has about as many tiles as the device holds resident wavefronts of the
+ * pass kernel (4*2*iters_per_pass..768 rows); batched solves use 64 rows
+ * below n = 512, else 192 (FP64) or 96.  An
  * autotuned entry for the grid's size class (sor_autotune for plain solves,
  * sor_autotune_batch for batched ones) takes precedence.  Results do not
  * depend on the tiling. */
@@ -347,10 +348,11 @@ sor_status sor_batch_solve_f64(sor_ctx *ctx, const sor_grid_desc *grids,
 
 /*
  * Tiling autotuner for plain solves: times blocked passes of every candidate
- * tiling (iterations per pass x rows per tile) on a scratch n x n grid of the
- * given storage precision (64 or 32 bits) with HIP events, stores the fastest
- * in the context's plain-solve tuning table for n's size class (side rounded
- * to the nearest half power of two), and returns it in *best (may be NULL).
+ * tiling (1..8 iterations per pass x 16..768 rows per tile) on a scratch
+ * n x n Laplace grid of the given storage precision (64 or 32 bits) with HIP
+ * events, stores the fastest in the context's plain-solve tuning table for
+ * n's size class (side rounded to the nearest half power of two), and returns
+ * it in *best (may be NULL).
  * Later plain solves of that precision and class use it.  Only timing is
  * measured: results never depend on the tiling.
  */
