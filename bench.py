@@ -409,11 +409,11 @@ def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
 def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
     """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1): update rate
     on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
-    around each iteration's launches; 16 algorithmic bytes per update against
+    around each pass; 16 algorithmic bytes per update against
     the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
     128^2 grid next to red-black, all at their best omega (Jacobi: 1).
-    Jacobi runs one iteration per launch; four-colour its blocked passes of
-    several iterations each."""
+    Both run their blocked passes of several iterations each (Jacobi 8,
+    four-colour 4 by default)."""
     from workloads import laplace_random_boundary
     g = laplace_random_boundary(n)
     b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")

@@ -220,14 +220,15 @@ enum {
  * sor_solve_f64 with the given ordering: same arguments, layout, ownership,
  * update expression ((N+S)+(W+E) [+h*h*f]) * 0.25 in increment form,
  * stopping rule (Algorithm 1), results and errors; SOR_EINVAL for an unknown
- * ordering.  JACOBI runs one iteration per launch, from one padded grid into
- * a second, and ignores the context's kernel and tiling settings.
- * FOUR_COLOUR follows the context's kernel: SOR_KERNEL_BLOCKED (default)
- * applies several iterations per HBM pass like the red-black blocked kernel
- * (three colour sweeps per iteration instead of two half-sweeps; tiling from
- * sor_ctx_set_variant_tiling), SOR_KERNEL_SIMPLE runs three launches per
- * iteration in place.  Results are bit-identical either way; out->passes
- * counts launches that did work (iterations for the simple kernel).
+ * ordering.  Both follow the context's kernel.  SOR_KERNEL_BLOCKED (default)
+ * applies several iterations per HBM pass like the red-black blocked kernel,
+ * from one padded grid into a second (FOUR_COLOUR: three colour sweeps per
+ * iteration instead of two half-sweeps; JACOBI: one sweep of every cell from
+ * the previous iterate per iteration; tiling from
+ * sor_ctx_set_variant_tiling).  SOR_KERNEL_SIMPLE runs one iteration per
+ * launch for JACOBI (grid to grid) and three launches per iteration in place
+ * for FOUR_COLOUR.  Results are bit-identical either way; out->passes counts
+ * launches that did work (iterations for the simple kernels).
  */
 sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
                                  const double *boundary, const double *rhs, int32_t n,
@@ -235,13 +236,15 @@ sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
                                  int64_t check_every, void *stream, sor_result *out,
                                  double *max_hist);
 
-/* Tiling of the blocked four-colour kernel (ordering SOR_ORDER_FOUR_COLOUR;
- * other orderings: SOR_EINVAL).  iters_per_pass in 1..4 (each is 3 colour
- * sweeps, so 4 has the stage depth of red-black's 6), seg_rows even in
- * 8..1024; 0 in a field means "keep".  A new context uses 4 and picks
- * seg_rows from the grid side as sor_ctx_set_tiling describes.  Results do
- * not depend on the tiling.  sor_ctx_get_variant_tiling reports the setting
- * (seg_rows 0 until one is set). */
+/* Tiling of the blocked kernel of ordering SOR_ORDER_FOUR_COLOUR or
+ * SOR_ORDER_JACOBI (SOR_ORDER_RED_BLACK uses sor_ctx_set_tiling; others:
+ * SOR_EINVAL).  iters_per_pass in 1..4 for FOUR_COLOUR (each is 3 colour
+ * sweeps, so 4 has the stage depth of red-black's 6) and 1..8 for JACOBI
+ * (one sweep each); seg_rows even in 8..1024; 0 in a field means "keep".  A
+ * new context uses 4 (FOUR_COLOUR) and 8 (JACOBI) and picks seg_rows from
+ * the grid side as sor_ctx_set_tiling describes.  Results do not depend on
+ * the tiling.  sor_ctx_get_variant_tiling reports the setting (seg_rows 0
+ * until one is set). */
 sor_status sor_ctx_set_variant_tiling(sor_ctx *ctx, int32_t ordering, const sor_tiling *t);
 sor_status sor_ctx_get_variant_tiling(const sor_ctx *ctx, int32_t ordering, sor_tiling *t);
 

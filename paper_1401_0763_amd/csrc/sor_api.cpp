@@ -151,15 +151,22 @@ sor_status prof_events(sor_ctx *c, size_t k, hipEvent_t *a, hipEvent_t *b) {
   return SOR_OK;
 }
 
-// Tiling of a four-colour solve: the context's setting, with seg_rows from
-// auto_seg_rows when none was set.
-sor_tiling c4_tiling(sor_ctx *c, int n, bool pois) {
-  sor_tiling t = c->tiling_c4;
-  if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, kF64, n, t.iters_per_pass, pois, 1);
+// Pass ordering of the blocked tile for a solve ordering (1 four-colour,
+// 2 Jacobi), or -1.
+int pass_ordering(int32_t ordering) {
+  return ordering == SOR_ORDER_FOUR_COLOUR ? 1 : ordering == SOR_ORDER_JACOBI ? 2 : -1;
+}
+
+// Tiling of a four-colour or Jacobi solve (pass ordering ord): the context's
+// setting, with seg_rows from auto_seg_rows when none was set.
+sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
+  sor_tiling t = c->tiling_var[ord];
+  if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, kF64, n, t.iters_per_pass, pois, ord);
   return t;
 }
 
-// Run SOR sweeps (red-black, or four-colour with ord 1 and FP64 grids) on the
+// Run SOR sweeps (red-black; four-colour with ord 1 or Jacobi with ord 2 on
+// FP64 grids, where the simple kernel is the in-place four-colour one) on the
 // packed grids A/B (same layout L) until the stopping rule or max_iters.  On
 // return *result_grid is the grid holding the final iterate.  hist (host, may
 // be null) receives per-iteration changes.
@@ -169,9 +176,9 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       void **result_grid, int ord = 0) {
   Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
   HIP_TRY(c, launch_ctl_reset(ctl, s));
-  const sor_tiling tl = ord ? c4_tiling(c, L.n, F != nullptr)
+  const sor_tiling tl = ord ? variant_tiling(c, ord, L.n, F != nullptr)
                             : tuned_tiling(c, prec, L.n, F != nullptr);
-  const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2;   // Jacobi: ping-pong only
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 
@@ -199,7 +206,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         if (pst != SOR_OK) return pst;
         HIP_TRY(c, hipEventRecord(e0, s));
       }
-      if (simple && ord) {
+      if (simple && ord == 1) {
         HIP_TRY(c, launch_colour4_iteration((double *)cur, (const double *)F, L.pitch, L.n,
                                             omega, ctl, sc, s));
       } else if (simple) {
@@ -628,6 +635,7 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
   const Layout L = make_layout(n, kF64);
   const size_t bytes = (size_t)L.elems() * sizeof(double);
   const bool jacobi = ordering == SOR_ORDER_JACOBI;
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE;
   if ((st = ensure(c, kGridA64, bytes)) || (st = ensure(c, kGridB64, bytes))) return st;
   if (rhs && (st = ensure(c, kF64Buf, bytes))) return st;
   double *A = origin<double>(c, kGridA64, L), *B = origin<double>(c, kGridB64, L);
@@ -640,7 +648,7 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
   out->rel_residual = NAN;
   const Sched sc{max_iters, check_every, tol};
   void *res_grid = A;
-  if (jacobi) {
+  if (jacobi && simple) {
     st = run_iteration_loop(c, sc, s, out, hist, [&](long long, long long k, int &iters) {
       iters = 1;
       const bool even = (k & 1) == 0;
@@ -649,7 +657,8 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
     });
     res_grid = (out->passes & 1) ? B : A;
   } else {
-    st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid, 1);
+    st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid,
+                    pass_ordering(ordering));
   }
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));
@@ -661,12 +670,13 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
 sor_status sor_ctx_set_variant_tiling(sor_ctx *c, int32_t ordering, const sor_tiling *t) {
   if (!c || !t) return SOR_EINVAL;
   c->err.clear();
-  if (ordering != SOR_ORDER_FOUR_COLOUR)
-    return fail(c, SOR_EINVAL, "ordering %d has no blocked tiling", ordering);
-  sor_tiling nt = c->tiling_c4;
+  const int ord = pass_ordering(ordering);
+  if (ord < 0) return fail(c, SOR_EINVAL, "ordering %d has no blocked tiling", ordering);
+  sor_tiling nt = c->tiling_var[ord];
   if (t->iters_per_pass) {
-    if (!blocked_c4_T_supported(t->iters_per_pass))
-      return fail(c, SOR_EINVAL, "four-colour iters_per_pass must be in 1..%d", kTMaxC4);
+    if (!blocked_ord_T_supported(ord, t->iters_per_pass))
+      return fail(c, SOR_EINVAL, "iters_per_pass must be in 1..%d for this ordering",
+                  ord == 1 ? kTMaxC4 : kTMax);
     nt.iters_per_pass = t->iters_per_pass;
   }
   if (t->seg_rows) {
@@ -674,13 +684,13 @@ sor_status sor_ctx_set_variant_tiling(sor_ctx *c, int32_t ordering, const sor_ti
       return fail(c, SOR_EINVAL, "seg_rows must be even and in 8..1024");
     nt.seg_rows = t->seg_rows;
   }
-  c->tiling_c4 = nt;
+  c->tiling_var[ord] = nt;
   return SOR_OK;
 }
 
 sor_status sor_ctx_get_variant_tiling(const sor_ctx *c, int32_t ordering, sor_tiling *t) {
-  if (!c || !t || ordering != SOR_ORDER_FOUR_COLOUR) return SOR_EINVAL;
-  *t = c->tiling_c4;
+  if (!c || !t || pass_ordering(ordering) < 0) return SOR_EINVAL;
+  *t = c->tiling_var[pass_ordering(ordering)];
   return SOR_OK;
 }
 

@@ -81,7 +81,7 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord) {
       cus = 256;
     c->cus = cus;
   }
-  int &occ = ord ? c->occ_c4[T][pois ? 1 : 0] : c->occ[prec][T][pois ? 1 : 0];
+  int &occ = ord ? c->occ_var[ord][T][pois ? 1 : 0] : c->occ[prec][T][pois ? 1 : 0];
   if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, T, pois, ord));
   const BlockGeom gm = block_geom(prec, T, ord);
   const long long strips = (n + 1 + gm.CW - 1) / gm.CW;

@@ -1,0 +1,8 @@
+// Blocked Jacobi pass, FP64 storage, 6 iteration(s) per pass.
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF64, 6, 2>(const GridView &, Ctl *,
+                                                 const Sched &, hipStream_t);
+template int blocked_blocks_per_cu<kF64, 6, 2>(bool);
+}  // namespace sor

@@ -350,14 +350,56 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
 SOR_EXTERN_BLOCKED_ALL(kF64)
 SOR_EXTERN_BLOCKED_ALL(kF32)
 SOR_EXTERN_BLOCKED_ALL(kF16)
-#define SOR_EXTERN_BLOCKED_C4(T)                                               \
-  extern template hipError_t launch_blocked_PT<kF64, T, 1>(                    \
+#define SOR_EXTERN_BLOCKED_ORD(T, ORD)                                         \
+  extern template hipError_t launch_blocked_PT<kF64, T, ORD>(                  \
       const GridView &, Ctl *, const Sched &, hipStream_t);                    \
-  extern template int blocked_blocks_per_cu<kF64, T, 1>(bool);
-SOR_EXTERN_BLOCKED_C4(1)
-SOR_EXTERN_BLOCKED_C4(2)
-SOR_EXTERN_BLOCKED_C4(3)
-SOR_EXTERN_BLOCKED_C4(4)
+  extern template int blocked_blocks_per_cu<kF64, T, ORD>(bool);
+SOR_EXTERN_BLOCKED_ORD(1, 1) SOR_EXTERN_BLOCKED_ORD(2, 1)
+SOR_EXTERN_BLOCKED_ORD(3, 1) SOR_EXTERN_BLOCKED_ORD(4, 1)
+SOR_EXTERN_BLOCKED_ORD(1, 2) SOR_EXTERN_BLOCKED_ORD(2, 2)
+SOR_EXTERN_BLOCKED_ORD(3, 2) SOR_EXTERN_BLOCKED_ORD(4, 2)
+SOR_EXTERN_BLOCKED_ORD(5, 2) SOR_EXTERN_BLOCKED_ORD(6, 2)
+SOR_EXTERN_BLOCKED_ORD(7, 2) SOR_EXTERN_BLOCKED_ORD(8, 2)
+
+// Passes of the other orderings (FP64 only).
+template <int ORD>
+static hipError_t launch_blocked_ord(int T, const GridView &v, Ctl *ctl, const Sched &sc,
+                                     hipStream_t s) {
+  switch (T) {
+    case 1: return launch_blocked_PT<kF64, 1, ORD>(v, ctl, sc, s);
+    case 2: return launch_blocked_PT<kF64, 2, ORD>(v, ctl, sc, s);
+    case 3: return launch_blocked_PT<kF64, 3, ORD>(v, ctl, sc, s);
+    case 4: return launch_blocked_PT<kF64, 4, ORD>(v, ctl, sc, s);
+  }
+  if constexpr (ORD == 2) {
+    switch (T) {
+      case 5: return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s);
+      case 6: return launch_blocked_PT<kF64, 6, ORD>(v, ctl, sc, s);
+      case 7: return launch_blocked_PT<kF64, 7, ORD>(v, ctl, sc, s);
+      case 8: return launch_blocked_PT<kF64, 8, ORD>(v, ctl, sc, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int ORD>
+static int blocked_blocks_per_cu_ord(int T, bool pois) {
+  switch (T) {
+    case 1: return blocked_blocks_per_cu<kF64, 1, ORD>(pois);
+    case 2: return blocked_blocks_per_cu<kF64, 2, ORD>(pois);
+    case 3: return blocked_blocks_per_cu<kF64, 3, ORD>(pois);
+    case 4: return blocked_blocks_per_cu<kF64, 4, ORD>(pois);
+  }
+  if constexpr (ORD == 2) {
+    switch (T) {
+      case 5: return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
+      case 6: return blocked_blocks_per_cu<kF64, 6, ORD>(pois);
+      case 7: return blocked_blocks_per_cu<kF64, 7, ORD>(pois);
+      case 8: return blocked_blocks_per_cu<kF64, 8, ORD>(pois);
+    }
+  }
+  return 0;
+}
 
 template <int P>
 static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
@@ -393,13 +435,7 @@ static int blocked_blocks_per_cu_P(int T, bool pois) {
 int blocked_blocks_per_cu(int prec, int T, bool pois, int ord) {
   if (ord) {
     if (prec != kF64) return 0;
-    switch (T) {
-      case 1: return blocked_blocks_per_cu<kF64, 1, 1>(pois);
-      case 2: return blocked_blocks_per_cu<kF64, 2, 1>(pois);
-      case 3: return blocked_blocks_per_cu<kF64, 3, 1>(pois);
-      case 4: return blocked_blocks_per_cu<kF64, 4, 1>(pois);
-    }
-    return 0;
+    return ord == 1 ? blocked_blocks_per_cu_ord<1>(T, pois) : blocked_blocks_per_cu_ord<2>(T, pois);
   }
   switch (prec) {
     case kF64: return blocked_blocks_per_cu_P<kF64>(T, pois);
@@ -413,19 +449,15 @@ bool blocked_T_supported(int T) {
   return T >= 1 && T <= kTMax;
 }
 
-bool blocked_c4_T_supported(int T) { return T >= 1 && T <= kTMaxC4; }
+bool blocked_ord_T_supported(int ord, int T) {
+  return T >= 1 && T <= (ord == 1 ? kTMaxC4 : kTMax);
+}
 
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s, int ord) {
   if (ord) {
     if (prec != kF64) return hipErrorInvalidValue;
-    switch (T) {
-      case 1: return launch_blocked_PT<kF64, 1, 1>(v, ctl, sc, s);
-      case 2: return launch_blocked_PT<kF64, 2, 1>(v, ctl, sc, s);
-      case 3: return launch_blocked_PT<kF64, 3, 1>(v, ctl, sc, s);
-      case 4: return launch_blocked_PT<kF64, 4, 1>(v, ctl, sc, s);
-    }
-    return hipErrorInvalidValue;
+    return ord == 1 ? launch_blocked_ord<1>(T, v, ctl, sc, s) : launch_blocked_ord<2>(T, v, ctl, sc, s);
   }
   switch (prec) {
     case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s);

@@ -46,8 +46,10 @@ struct sor_ctx {
   sor::BatchState *batch = nullptr;                    // batched-solve state
   int cus = 0;                                         // compute units (lazy)
   int occ[3][sor::kTMax + 1][2] = {};                   // pass blocks per CU (lazy)
-  sor_tiling tiling_c4 = {4, 0};                       // four-colour passes; seg 0: by size
-  int occ_c4[sor::kTMaxC4 + 1][2] = {};                // four-colour pass blocks per CU
+  // Blocked passes of the other orderings, by pass ordering (1 four-colour,
+  // 2 Jacobi; 0 unused); seg 0: by size.
+  sor_tiling tiling_var[3] = {{0, 0}, {4, 0}, {8, 0}};
+  int occ_var[3][sor::kTMax + 1][2] = {};              // their pass blocks per CU (lazy)
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
   int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)
 };

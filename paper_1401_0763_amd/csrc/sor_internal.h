@@ -252,14 +252,15 @@ hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
 // Blocked pass of T iterations from v.in into v.out: red-black (ord 0, T in
-// 1..kTMax, every precision) or four-colour (ord 1, T in 1..kTMaxC4, FP64); the
-// view's nstrips/nseg must match T and the ordering.  ctl == nullptr runs
-// without maxima, verdict or early exit.
+// 1..kTMax, every precision), four-colour (ord 1, T in 1..kTMaxC4, FP64) or
+// Jacobi (ord 2, T in 1..kTMax, FP64); the view's nstrips/nseg must match T
+// and the ordering.  ctl == nullptr runs without maxima, verdict or early
+// exit.
 constexpr int kTMaxC4 = 4;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s, int ord = 0);
 bool blocked_T_supported(int T);
-bool blocked_c4_T_supported(int T);
+bool blocked_ord_T_supported(int ord, int T);
 // Pass-kernel workgroups (wavefronts) resident per CU; 0 if the query fails.
 int blocked_blocks_per_cu(int prec, int T, bool pois, int ord = 0);
 // Simple kernel: one launch per colour, in place on v.in (v.out ignored).

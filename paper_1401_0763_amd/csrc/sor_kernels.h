@@ -223,11 +223,14 @@ __host__ __device__ constexpr int blocked_window_rows(int T) {
   return ((2 * T + SOR_PREFETCH + 2) + 1) / 2 * 2;
 }
 
-// Stage pipelines of the blocked tile by ordering: red-black applies 2
-// half-sweeps per iteration; the four-colour ordering 3 (colour 0, colours 1
-// and 2, colour 3).  The row halo is the stage count rounded up to even, so a
-// tile's first loaded row keeps the parity of its first core row.
-__host__ __device__ constexpr int order_stages(int ord, int T) { return (ord ? 3 : 2) * T; }
+// Stage pipelines of the blocked tile by ordering: red-black (0) applies 2
+// half-sweeps per iteration; the four-colour ordering (1) 3 (colour 0,
+// colours 1 and 2, colour 3); Jacobi (2) one sweep of every cell from the
+// previous iterate.  The row halo is the stage count rounded up to even, so
+// a tile's first loaded row keeps the parity of its first core row.
+__host__ __device__ constexpr int order_stages(int ord, int T) {
+  return (ord == 0 ? 2 : ord == 1 ? 3 : 1) * T;
+}
 __host__ __device__ constexpr int order_row_halo(int ord, int T) {
   return (order_stages(ord, T) + 1) / 2 * 2;
 }
@@ -283,7 +286,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   using st = typename PT<P>::st;
   using ct = typename PT<P>::ct;
   constexpr int V = PT<P>::V;
-  static_assert(ORD == 0 || P == kF64, "four-colour passes are instantiated for FP64");
+  static_assert(ORD == 0 || P == kF64, "other orderings are instantiated for FP64");
   constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
   constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
@@ -368,6 +371,24 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
   if constexpr (ORD == 0) xs[0] = lane_permute(from_hi, w[1][0]);
+  // Jacobi: every stage needs both cross-lane neighbours (xs from the lane
+  // below, xr from the lane above) and the row above its row at its own
+  // input level (pv), which the stage itself overwrote one step earlier.
+  constexpr int SJ = ORD == 2 ? S : 1;
+  ct xr[SJ];
+  ct pv[SJ][V];
+#pragma unroll
+  for (int k = 0; k < SJ; ++k) {
+    xr[k] = (ct)0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) pv[k][v] = (ct)0;
+  }
+  if constexpr (ORD == 2) {
+    xs[0] = lane_permute(from_lo, w[1][V - 1]);
+    xr[0] = lane_permute(from_hi, w[1][0]);
+#pragma unroll
+    for (int v = 0; v < V; ++v) pv[0][v] = w[0][v];
+  }
 
   // Wait here for the prologue's loads and permute.  The loop head joins
   // this path with the loop's back edge; without the wait the compiler takes
@@ -423,7 +444,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         // sink it next to its use a step later and wait for it there).
         __builtin_amdgcn_sched_barrier(0);
       });
-      } else {
+      } else if constexpr (ORD == 1) {
       // Four-colour ordering: stage k is colour sweep k mod 3 of iteration
       // k/3 (colour 0 = even row and column, then colours 1 and 2 = the
       // black cells, then colour 3 = odd row and column).  Row q = r-k has
@@ -471,6 +492,43 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         }
         __builtin_amdgcn_sched_barrier(0);
       });
+      } else {
+      // Jacobi: stage k is iteration k and updates every cell of row r-k
+      // from level k of the rows above (pv[k]), at (its own, before any
+      // write) and below (just updated by stage k-1), and of the cells in
+      // the neighbouring lanes (sent one step earlier).
+      ct xrn[S];
+      xn[0] = lane_permute(from_lo, w[(i + 2) % W][V - 1]);
+      xrn[0] = lane_permute(from_hi, w[(i + 2) % W][0]);
+      static_for<0, S>([&](auto K) __attribute__((always_inline)) {
+        constexpr int k = decltype(K)::value;
+        constexpr int sq = ((i + 1 - k) % W + W) % W;
+        constexpr int sd = (sq + 1) % W;
+        ct nw[V];
+        static_for<0, V>([&](auto VV) __attribute__((always_inline)) {
+          constexpr int v = decltype(VV)::value;
+          const ct self = w[sq][v];
+          const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
+          const ct right = v == V - 1 ? xr[k] : w[sq][v == V - 1 ? 0 : v + 1];
+          ct s = (pv[k][v] + w[sd][v]) + (left + right);
+          if constexpr (POIS) s = s + fw[sq][v];
+          const ct dg = vfma((ct)0.25, s, -self);
+          nw[v] = vfma(omc[v] * wr[sq], dg, self);
+          m[k] = vmax(m[k], vabs(nw[v] - self) * wc[sq]);
+        });
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          pv[k][v] = w[sq][v];
+          w[sq][v] = nw[v];
+        }
+        if constexpr (k + 1 < S) {
+          xn[k + 1] = lane_permute(from_lo, nw[V - 1]);
+          xrn[k + 1] = lane_permute(from_hi, nw[0]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+#pragma unroll
+      for (int k = 0; k < S; ++k) xr[k] = xrn[k];
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) xs[k] = xn[k];
@@ -523,6 +581,13 @@ template <int P, int T, bool POIS>
 __global__ __launch_bounds__(64) void blocked_pass_c4_kernel(GridView g, Ctl *ctl,
                                                              Sched sc) {
   blocked_pass_body<P, T, POIS, 1>(g, ctl, sc);
+}
+
+// Jacobi passes.
+template <int P, int T, bool POIS>
+__global__ __launch_bounds__(64) void blocked_pass_jacobi_kernel(GridView g, Ctl *ctl,
+                                                                 Sched sc) {
+  blocked_pass_body<P, T, POIS, 2>(g, ctl, sc);
 }
 
 // Device-scope scalar loads and stores (relaxed agent-scope atomics, i.e.
@@ -621,12 +686,15 @@ __device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
   return true;
 }
 
-// The pass kernel of an ordering, as a type (for the launchers below).
-template <int P, int T, bool POIS> struct BPK {
+// The pass kernel of an ordering (for the launchers below).
+template <int P, int T, bool POIS, int ORD> struct PassKernel {
   static constexpr auto k = blocked_pass_kernel<P, T, POIS>;
 };
-template <int P, int T, bool POIS> struct BPK4 {
+template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 1> {
   static constexpr auto k = blocked_pass_c4_kernel<P, T, POIS>;
+};
+template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 2> {
+  static constexpr auto k = blocked_pass_jacobi_kernel<P, T, POIS>;
 };
 
 // Host-side launch of the blocked pass for one (precision, T); each pair is
@@ -637,11 +705,9 @@ hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
                              hipStream_t s) {
   const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
   if (v.F)
-    hipLaunchKernelGGL((std::conditional_t<ORD == 0, BPK<P, T, true>, BPK4<P, T, true>>::k),
-                       grid, dim3(64), 0, s, v, ctl, sc);
+    hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
   else
-    hipLaunchKernelGGL((std::conditional_t<ORD == 0, BPK<P, T, false>, BPK4<P, T, false>>::k),
-                       grid, dim3(64), 0, s, v, ctl, sc);
+    hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
   return hipGetLastError();
 }
 
@@ -651,13 +717,9 @@ int blocked_blocks_per_cu(bool pois) {
   int nb = 0;
   const hipError_t e =
       pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(
-                          std::conditional_t<ORD == 0, BPK<P, T, true>, BPK4<P, T, true>>::k),
-                 64, 0)
+                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, true, ORD>::k), 64, 0)
            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(
-                          std::conditional_t<ORD == 0, BPK<P, T, false>, BPK4<P, T, false>>::k),
-                 64, 0);
+                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, false, ORD>::k), 64, 0);
   return e == hipSuccess ? nb : 0;
 }
 

@@ -135,73 +135,90 @@ def test_red_black_ordering_is_solve_f64_and_errors(sor, ctx):
         assert r.status == sor.ENONFINITE, name
 
 
-# Blocked four-colour passes: depth 1..4 (truncated passes when fewer
+# Blocked passes of both orderings: every depth (truncated passes when fewer
 # iterations remain), segment heights that do and do not divide the grid, and
 # strips with a ragged last one.
-C4_TILINGS = [(1, 8), (2, 14), (3, 30), (4, 48), (4, 202), (3, 64), (2, 1024)]
+BLOCKED_TILINGS = [
+    (2, "four-colour", 1, 8), (2, "four-colour", 2, 14), (2, "four-colour", 3, 30),
+    (2, "four-colour", 4, 48), (2, "four-colour", 4, 202), (2, "four-colour", 3, 64),
+    (2, "four-colour", 2, 1024),
+    (1, "jacobi", 1, 8), (1, "jacobi", 2, 14), (1, "jacobi", 3, 30), (1, "jacobi", 4, 48),
+    (1, "jacobi", 5, 40), (1, "jacobi", 6, 202), (1, "jacobi", 7, 64), (1, "jacobi", 8, 16),
+    (1, "jacobi", 8, 1024)]
 
 
-@pytest.mark.parametrize("T,seg", C4_TILINGS)
+@pytest.mark.parametrize("ordering,name,T,seg", BLOCKED_TILINGS)
 @pytest.mark.parametrize("n,with_f,iters", [
     (1, False, 3), (5, True, 9), (61, True, 11), (130, False, 13), (300, True, 10),
     (513, False, 7)])
-def test_four_colour_blocked_tilings_bitwise(sor, ctx, T, seg, n, with_f, iters):
+def test_blocked_tilings_bitwise(sor, ctx, ordering, name, T, seg, n, with_f, iters):
     g = random_small(900 + n + T, n, with_f=with_f, nonzero_u0=True)
-    ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, T, seg)
-    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (T, seg)
-    _say(f"four-colour blocked T={T} seg={seg} n={n} f={with_f} iters={iters}")
-    ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, 1.37, 0.0, iters, 1, hist=True)
-    res, u = run(sor, ctx, 2, g, 1.37, 0.0, iters, 1)
+    ctx.set_variant_tiling(ordering, T, seg)
+    assert ctx.get_variant_tiling(ordering) == (T, seg)
+    _say(f"{name} blocked T={T} seg={seg} n={n} f={with_f} iters={iters}")
+    ref = oracle.variant_f64(ordering, g.u0, g.bdy, g.f, 1.37, 0.0, iters, 1, hist=True)
+    res, u = run(sor, ctx, ordering, g, 1.37, 0.0, iters, 1)
     assert res.status == sor.NOT_CONVERGED and res.iterations == iters
     assert res.passes == -(-iters // T)     # every pass did work (no early stop)
-    assert_bitwise(u, ref.u, f"four-colour blocked u T={T} seg={seg} n={n}")
-    assert_bitwise(np.array(res.hist), ref.mhist, f"four-colour blocked hist T={T} n={n}")
+    assert_bitwise(u, ref.u, f"{name} blocked u T={T} seg={seg} n={n}")
+    assert_bitwise(np.array(res.hist), ref.mhist, f"{name} blocked hist T={T} n={n}")
 
 
-@pytest.mark.parametrize("T", [2, 3, 4])
+@pytest.mark.parametrize("ordering,name,T", [
+    (2, "four-colour", 2), (2, "four-colour", 3), (2, "four-colour", 4),
+    (1, "jacobi", 3), (1, "jacobi", 8)])
 @pytest.mark.parametrize("K", [1, 3, 5])
-def test_four_colour_blocked_stop_inside_a_pass(sor, ctx, T, K):
+def test_blocked_stop_inside_a_pass(sor, ctx, ordering, name, T, K):
     """Checks that fall inside a pass: the pass is redone up to the stop from
     its intact input, so grid and change match the oracle's stop."""
     n = 90
     g = random_small(77 + K, n, with_f=True)
-    ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, T, 32)
-    for tol in (1e-3, 1e-7):
-        ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, g.omega, tol, 50000, K, hist=True)
-        _say(f"four-colour blocked T={T} K={K} tol={tol} ref_it={ref.iterations}")
+    omega = 1.0 if ordering == 1 else g.omega
+    ctx.set_variant_tiling(ordering, T, 32)
+    for tol in ((1e-2, 1e-4) if ordering == 1 else (1e-3, 1e-7)):
+        ref = oracle.variant_f64(ordering, g.u0, g.bdy, g.f, omega, tol, 50000, K, hist=True)
+        _say(f"{name} blocked T={T} K={K} tol={tol} ref_it={ref.iterations}")
         assert ref.status == oracle.OK
-        res, u = run(sor, ctx, 2, g, g.omega, tol, 50000, K)
+        res, u = run(sor, ctx, ordering, g, omega, tol, 50000, K)
         assert res.status == sor.OK and res.iterations == ref.iterations
         assert res.final_max_delta == ref.final_max_delta
-        assert_bitwise(u, ref.u, f"four-colour blocked u T={T} K={K} tol={tol}")
-        assert_bitwise(np.array(res.hist), ref.mhist, f"four-colour blocked hist T={T} K={K}")
+        assert_bitwise(u, ref.u, f"{name} blocked u T={T} K={K} tol={tol}")
+        assert_bitwise(np.array(res.hist), ref.mhist, f"{name} blocked hist T={T} K={K}")
 
 
-def test_four_colour_simple_and_blocked_agree(sor, ctx):
-    """The three-launch in-place kernel and the blocked passes give the same
-    bits (and the oracle's)."""
+@pytest.mark.parametrize("ordering,name,default_T", [(2, "four-colour", 4), (1, "jacobi", 8)])
+def test_simple_and_blocked_agree(sor, ctx, ordering, name, default_T):
+    """The one-iteration-per-launch kernels and the blocked passes give the
+    same bits (and the oracle's)."""
     n = 257
     g = random_small(31, n, with_f=True, nonzero_u0=True)
-    ref = oracle.variant_f64(2, g.u0, g.bdy, g.f, g.omega, 0.0, 14, 1, hist=True)
+    ref = oracle.variant_f64(ordering, g.u0, g.bdy, g.f, g.omega, 0.0, 14, 1, hist=True)
     ctx.set_kernel(sor.KERNEL_SIMPLE)
-    res_s, u_s = run(sor, ctx, 2, g, g.omega, 0.0, 14, 1)
+    res_s, u_s = run(sor, ctx, ordering, g, g.omega, 0.0, 14, 1)
     assert res_s.passes == 14
     ctx.set_kernel(sor.KERNEL_BLOCKED)
-    res_b, u_b = run(sor, ctx, 2, g, g.omega, 0.0, 14, 1)
-    assert res_b.passes == 4            # 4 + 4 + 4 + 2 iterations at the default depth 4
-    assert_bitwise(u_s, ref.u, "four-colour simple")
-    assert_bitwise(u_b, ref.u, "four-colour blocked")
-    assert_bitwise(np.array(res_s.hist), ref.mhist, "four-colour simple hist")
-    assert_bitwise(np.array(res_b.hist), ref.mhist, "four-colour blocked hist")
+    res_b, u_b = run(sor, ctx, ordering, g, g.omega, 0.0, 14, 1)
+    assert res_b.passes == -(-14 // default_T)
+    assert_bitwise(u_s, ref.u, f"{name} simple")
+    assert_bitwise(u_b, ref.u, f"{name} blocked")
+    assert_bitwise(np.array(res_s.hist), ref.mhist, f"{name} simple hist")
+    assert_bitwise(np.array(res_b.hist), ref.mhist, f"{name} blocked hist")
 
 
-def test_four_colour_tiling_validation(sor, ctx):
+def test_variant_tiling_validation(sor, ctx):
     assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 0)
-    for bad in [(5, 0), (0, 7), (0, 6), (0, 1026), (-1, 0)]:
+    assert ctx.get_variant_tiling(sor.ORDER_JACOBI) == (8, 0)
+    for ordering, bad in [(sor.ORDER_FOUR_COLOUR, (5, 0)), (sor.ORDER_JACOBI, (9, 0))]:
         with pytest.raises(sor.SorError):
-            ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, *bad)
-    for ordering in (sor.ORDER_RED_BLACK, sor.ORDER_JACOBI, 7):
+            ctx.set_variant_tiling(ordering, *bad)
+    for bad in [(0, 7), (0, 6), (0, 1026), (-1, 0)]:
+        for ordering in (sor.ORDER_FOUR_COLOUR, sor.ORDER_JACOBI):
+            with pytest.raises(sor.SorError):
+                ctx.set_variant_tiling(ordering, *bad)
+    for ordering in (sor.ORDER_RED_BLACK, 7):
         with pytest.raises(sor.SorError):
             ctx.set_variant_tiling(ordering, 2, 64)
     ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, 0, 96)
     assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 96)
+    ctx.set_variant_tiling(sor.ORDER_JACOBI, 5, 0)
+    assert ctx.get_variant_tiling(sor.ORDER_JACOBI) == (5, 0)
