@@ -11,8 +11,8 @@ passes with device-side stopping checks, unpack).
 
 Output: one JSON line with GLUP/s (giga lattice-site updates per second), the
 dominant kernel's roofline position, and the CPU oracle's rate on the host
-cores.  The sweep applies 6 iterations per pass over HBM, so it is bound by
-vector FP64 arithmetic, not by HBM: the roofline reports algorithmic FP64
+cores.  The sweep applies 7 iterations per pass over HBM, so HBM traffic is
+a fraction of the algorithmic bytes: the roofline reports algorithmic FP64
 operations per lattice update (9: three adds for the neighbour sum, the
 quarter, the difference, the relaxation product, the update, the change and
 its running maximum) over the HIP-event-timed kernel time, against the
@@ -358,7 +358,7 @@ def form_paper(sor, ctx, torch, n=4096):
 def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
     """The 3-D extension (7-point stencil on the unit cube): 256^3 interior
     cells, random boundary faces, omega_opt; a fixed iteration count for the
-    update rate (kernel time from HIP events around each launch), then a
+    update rate (kernel time from HIP events around each run of launches), then a
     solve to 1e-8 checked every 10 iterations."""
     from workloads import random_cube
     g = random_cube(21, n, with_f=False)
@@ -409,7 +409,7 @@ def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
 def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
     """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1): update rate
     on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
-    around each pass; 16 algorithmic bytes per update against
+    around each run of passes; 16 algorithmic bytes per update against
     the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
     128^2 grid next to red-black, all at their best omega (Jacobi: 1).
     Both run their blocked passes of several iterations each (Jacobi 8,

@@ -133,10 +133,14 @@ sor_status sor_ctx_get_tiling(const sor_ctx *ctx, int32_t bits, sor_tiling *t);
 sor_status sor_ctx_tiling_for(sor_ctx *ctx, int32_t bits, int32_t n, int32_t has_rhs,
                               sor_tiling *t);
 
-/* Kernel timing for measurement.  While profiling is on, every sweep-kernel
- * launch of the plain and mixed solves is bracketed by HIP events on the
- * caller's stream; passes that did work add their duration to a running
- * total.  sor_ctx_get_profile returns the total milliseconds and the number of
+/* Kernel timing for measurement.  While profiling is on, each run of sweep
+ * launches between two host checks of the plain, mixed, 3-D and ordering
+ * solves is bracketed by a pair of HIP events on the caller's stream (one
+ * pair per run rather than per launch, so that the events add no gaps between
+ * launches); the run's duration adds to a running total and its passes that
+ * did work to a launch count (passes that exited at once after the stopping
+ * rule was met, and the gaps between launches, fall inside the bracket).
+ * sor_ctx_get_profile returns the total milliseconds and the number of
  * timed launches since profiling was last switched on. */
 sor_status sor_ctx_set_profiling(sor_ctx *ctx, int32_t on);
 sor_status sor_ctx_get_profile(const sor_ctx *ctx, double *kernel_ms,

@@ -194,18 +194,18 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   for (;;) {
     const long long chunk_it0 = done;
     recs.clear();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof) {
+      sor_status pst = prof_events(c, 0, &e0, &e1);
+      if (pst != SOR_OK) return pst;
+      HIP_TRY(c, hipEventRecord(e0, s));
+    }
     // Enqueue up to `chunk` passes (a truncated pass when < T iterations remain).
     for (long long k = 0; k < chunk && done < sc.max_iters; ++k) {
       const int Tp = pass_depth(sc.max_iters - done, T);
       GridView v = simple ? base : view_for(base, prec, Tp, ord);
       v.in = cur;
       v.out = simple ? cur : oth;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c->prof) {
-        sor_status pst = prof_events(c, (size_t)k, &e0, &e1);
-        if (pst != SOR_OK) return pst;
-        HIP_TRY(c, hipEventRecord(e0, s));
-      }
       if (simple && ord == 1) {
         HIP_TRY(c, launch_colour4_iteration((double *)cur, (const double *)F, L.pitch, L.n,
                                             omega, ctl, sc, s));
@@ -215,23 +215,23 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord));
         std::swap(cur, oth);
       }
-      if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
       recs.push_back({v.in, v.out, done, Tp});
       done += Tp;
       if (done - chunk_it0 >= kHistCap - kTMax) break;
     }
+    if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     const Ctl &h = *c->host_ctl;
     const long long hist_end = h.stop ? h.stop_iter : done;
     if (c->prof) {
-      for (size_t k = 0; k < recs.size(); ++k) {
-        if (h.stop && recs[k].it0 >= h.stop_iter) break;   // exited early
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->events[2 * k], c->events[2 * k + 1]));
-        c->prof_ms += ms;
-        c->prof_launches += 1;
-      }
+      long long worked = 0;                 // passes of the chunk that did not exit early
+      for (const PassRec &r : recs)
+        if (!(h.stop && r.it0 >= h.stop_iter)) ++worked;
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+      c->prof_ms += ms;
+      c->prof_launches += worked;
     }
     if (hist) {
       for (long long it = chunk_it0 + 1; it <= std::min(hist_end, sc.max_iters); ++it)
@@ -333,34 +333,34 @@ sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_re
     const long long chunk_it0 = done;
     long long k = 0;
     pass_end.clear();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->prof) {
+      sor_status pst = prof_events(c, 0, &e0, &e1);
+      if (pst != SOR_OK) return pst;
+      HIP_TRY(c, hipEventRecord(e0, s));
+    }
     for (; k < chunk && done < sc.max_iters; ++k) {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (c->prof) {
-        sor_status pst = prof_events(c, (size_t)k, &e0, &e1);
-        if (pst != SOR_OK) return pst;
-        HIP_TRY(c, hipEventRecord(e0, s));
-      }
       int iters = 1;
       HIP_TRY(c, launch(done, npass, iters));
-      if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
       done += iters;
       npass += 1;
       pass_end.push_back(done);
       if (done - chunk_it0 >= kHistCap - 2) { ++k; break; }
     }
+    if (c->prof) HIP_TRY(c, hipEventRecord(e1, s));
     HIP_TRY(c, hipMemcpyAsync(c->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     const Ctl &h = *c->host_ctl;
     const long long hist_end = h.stop ? h.stop_iter : done;
     res->passes = h.passes_done;
     if (c->prof) {
-      for (long long j = 0; j < k; ++j) {
-        if (h.stop && (j == 0 ? chunk_it0 : pass_end[j - 1]) >= h.stop_iter) break;   // exited early
-        float ms = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&ms, c->events[2 * j], c->events[2 * j + 1]));
-        c->prof_ms += ms;
-        c->prof_launches += 1;
-      }
+      long long worked = 0;                 // passes of the chunk that did not exit early
+      for (long long j = 0; j < k; ++j)
+        if (!(h.stop && (j == 0 ? chunk_it0 : pass_end[j - 1]) >= h.stop_iter)) ++worked;
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+      c->prof_ms += ms;
+      c->prof_launches += worked;
     }
     if (hist)
       for (long long it = chunk_it0 + 1; it <= std::min(hist_end, sc.max_iters); ++it)
