@@ -238,7 +238,9 @@ class Context:
         self._check(self.lib.sor_ctx_set_profiling(self.handle, int(bool(on))))
 
     def profile(self) -> tuple[float, int]:
-        """(total sweep-kernel milliseconds, timed launches) since profiling on."""
+        """(total sweep-kernel milliseconds, timed launches) since profiling
+        was switched on; each run of launches between host checks is timed as
+        a whole."""
         ms = ctypes.c_double()
         k = ctypes.c_int64()
         self._check(self.lib.sor_ctx_get_profile(self.handle, ctypes.byref(ms),
@@ -266,19 +268,22 @@ class Context:
         return t.iters_per_pass, t.seg_rows
 
     def set_variant_tiling(self, ordering: int, iters_per_pass: int = 0, seg_rows: int = 0):
-        """Tiling of the blocked four-colour kernel (0 keeps a field)."""
+        """Tiling of the blocked kernel of ORDER_FOUR_COLOUR or ORDER_JACOBI
+        (0 keeps a field)."""
         t = _Tiling(int(iters_per_pass), int(seg_rows))
         self._check(self.lib.sor_ctx_set_variant_tiling(self.handle, int(ordering),
                                                         ctypes.byref(t)))
 
     def get_variant_tiling(self, ordering: int) -> tuple[int, int]:
+        """The blocked tiling of an ordering; seg_rows 0 means chosen per grid size."""
         t = _Tiling()
         self._check(self.lib.sor_ctx_get_variant_tiling(self.handle, int(ordering),
                                                         ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
 
     def get_tiling(self, bits: int) -> tuple[int, int]:
-        """The context's tiling; seg_rows 0 means chosen per grid size."""
+        """The context's tiling; 0 means chosen per solve (iters_per_pass by
+        the pass kernel's occupancy, seg_rows by the grid side)."""
         t = _Tiling()
         self._check(self.lib.sor_ctx_get_tiling(self.handle, int(bits), ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
