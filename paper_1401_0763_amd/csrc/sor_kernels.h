@@ -216,18 +216,14 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
   }
 }
 
-// Rows of the register window of a T-deep tile: the 2T stage rows, their
-// neighbours and the SOR_PREFETCH rows loaded ahead, rounded up to even.  The
-// row walk runs in chunks of this many steps.
-__host__ __device__ constexpr int blocked_window_rows(int T) {
-  return ((2 * T + SOR_PREFETCH + 2) + 1) / 2 * 2;
-}
-
 // Stage pipelines of the blocked tile by ordering: red-black (0) applies 2
 // half-sweeps per iteration; the four-colour ordering (1) 3 (colour 0,
 // colours 1 and 2, colour 3); Jacobi (2) one sweep of every cell from the
 // previous iterate.  The row halo is the stage count rounded up to even, so
-// a tile's first loaded row keeps the parity of its first core row.
+// a tile's first loaded row keeps the parity of its first core row.  The
+// register window holds the stage rows, their neighbours and the
+// SOR_PREFETCH rows loaded ahead, rounded up to even; the row walk runs in
+// chunks of that many steps.
 __host__ __device__ constexpr int order_stages(int ord, int T) {
   return (ord == 0 ? 2 : ord == 1 ? 3 : 1) * T;
 }
@@ -261,10 +257,14 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 //
 // Values near the strip and segment edges depend on cells outside the tile
 // and are wrong after enough stages (the dependency cone grows one cell per
-// half-sweep), so the tile loads a halo of A >= S columns and S rows on each
-// side and stores only its core (CW columns x seg_rows rows).  Input and
+// half-sweep), so the tile loads a halo of A >= S columns and H >= S rows on
+// each side and stores only its core (CW columns x seg_rows rows).  Input and
 // output are separate grids (ping-pong), so halos are read at the pass's
 // starting level whatever order tiles run in.
+//
+// The other orderings (ORD, FP64 only) run the same walk, window, halo and
+// stores with their own stage lists; they are described where they branch
+// off below.
 //
 // One branch-free body serves every tile.  Boundary and out-of-grid cells
 // must keep their value; they get a relaxation factor of 0 instead of omega
