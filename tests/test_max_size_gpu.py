@@ -156,3 +156,57 @@ def test_3d_largest_side_sampled_windows(sor):
     finally:
         ctx.close()
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("ordering,name,reach", [(1, "jacobi", 1), (2, "four-colour", 3)])
+def test_2d_orderings_largest_side_sampled_windows(sor, ordering, name, reach):
+    """The blocked Jacobi and four-colour passes at n = 65536.  An iteration
+    moves information by one cell (Jacobi) or at most three (one per colour
+    sweep of the four-colour ordering), so the window oracle is exact more
+    than reach * k cells inside the frozen ring; windows start at even rows
+    and columns, which keeps every cell's four-colour class."""
+    n = 65536
+    rw = 12                          # window: interior 2 rw - 1 cells per axis
+    m = 2 * rw - 1
+    core = slice(reach * K_ITERS + 1, m - (reach * K_ITERS + 1))
+    ctx = sor.Context(0)
+    try:
+        rng = np.random.default_rng(65537 + ordering)
+        bdy = rng.uniform(0.0, 100.0, size=4 * n)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(19 + ordering)
+        _say(f"2-D {name} n=65536: filling u0 on the device")
+        u = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=gen) * 100.0
+        corners = [(0, 0), (0, n + 1 - 2 * rw - 1), (n + 1 - 2 * rw - 1, 0),
+                   (n + 1 - 2 * rw - 1, n + 1 - 2 * rw - 1), (n // 2, n // 2 + 2),
+                   (1000, 0), (0, 31000), (40002, 2)]
+        top = (n + 1 - 2 * rw) & ~1        # last even corner whose ring fits
+        corners = [(min(a + (a & 1), top), min(b + (b & 1), top)) for a, b in corners]
+        before = {}
+        for a, b in corners:
+            lo_i, lo_j = max(a - 1, 0), max(b - 1, 0)
+            before[(a, b)] = u[lo_i:a + 2 * rw, lo_j:b + 2 * rw].cpu().numpy().copy()
+        omega = 1.0 if ordering == 1 else 2.0 / (1.0 + np.sin(np.pi / (n + 1)))
+        _say(f"2-D {name} n=65536: solving")
+        res = sor.solve_variant_f64(ordering, u, torch.tensor(bdy, dtype=torch.float64,
+                                                              device="cuda"),
+                                    None, omega, 0.0, K_ITERS, 1, hist=False, ctx=ctx)
+        assert res.status == sor.NOT_CONVERGED and res.iterations == K_ITERS
+        for a, b in corners:
+            _say(f"2-D {name} window at ({a}, {b})")
+            blk = before[(a, b)]
+            lo_i, lo_j = max(a - 1, 0), max(b - 1, 0)
+            val = full_value_2d(lambda i, j: blk[i - 1 - lo_i, j - 1 - lo_j], bdy, n)
+            w0 = np.array([[val(a + 1 + r, b + 1 + c) for c in range(m)] for r in range(m)])
+            wb = np.concatenate([[val(a, b + 1 + c) for c in range(m)],
+                                 [val(a + 2 * rw, b + 1 + c) for c in range(m)],
+                                 [val(a + 1 + r, b) for r in range(m)],
+                                 [val(a + 1 + r, b + 2 * rw) for r in range(m)]])
+            ref = oracle.variant_f64(ordering, w0, wb, None, omega, 0.0, K_ITERS, 1)
+            got = u[a:a + m, b:b + m].cpu().numpy()
+            assert np.array_equal(got[core, core].view(np.uint64),
+                                  ref.u[core, core].view(np.uint64)), (name, a, b)
+        del u
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
