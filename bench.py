@@ -413,7 +413,7 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
     the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
     128^2 grid next to red-black, all at their best omega (Jacobi: 1).
     Both run their blocked passes of several iterations each (Jacobi 8,
-    four-colour 4 by default)."""
+    four-colour 5 by default)."""
     from workloads import laplace_random_boundary
     g = laplace_random_boundary(n)
     b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")

@@ -242,13 +242,13 @@ sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
 
 /* Tiling of the blocked kernel of ordering SOR_ORDER_FOUR_COLOUR or
  * SOR_ORDER_JACOBI (SOR_ORDER_RED_BLACK uses sor_ctx_set_tiling; others:
- * SOR_EINVAL).  iters_per_pass in 1..4 for FOUR_COLOUR (each is 3 colour
- * sweeps, so 4 has the stage depth of red-black's 6) and 1..8 for JACOBI
- * (one sweep each); seg_rows even in 8..1024; 0 in a field means "keep".  A
- * new context uses 4 (FOUR_COLOUR) and 8 (JACOBI) and picks seg_rows from
- * the grid side as sor_ctx_set_tiling describes.  Results do not depend on
- * the tiling.  sor_ctx_get_variant_tiling reports the setting (seg_rows 0
- * until one is set). */
+ * SOR_EINVAL).  iters_per_pass in 1..5 for FOUR_COLOUR (each is 3 colour
+ * sweeps, so 5 has 15 stages, about the stage depth of red-black's 7) and
+ * 1..8 for JACOBI (one sweep each); seg_rows even in 8..1024; 0 in a field
+ * means "keep".  A new context uses 5 (FOUR_COLOUR) and 8 (JACOBI) and picks
+ * seg_rows from the grid side as sor_ctx_set_tiling describes.  Results do
+ * not depend on the tiling.  sor_ctx_get_variant_tiling reports the setting
+ * (seg_rows 0 until one is set). */
 sor_status sor_ctx_set_variant_tiling(sor_ctx *ctx, int32_t ordering, const sor_tiling *t);
 sor_status sor_ctx_get_variant_tiling(const sor_ctx *ctx, int32_t ordering, sor_tiling *t);
 

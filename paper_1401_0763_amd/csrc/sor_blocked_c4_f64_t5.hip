@@ -1,0 +1,8 @@
+// Blocked four-colour SOR pass, FP64 storage, 5 iteration(s) per pass.
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF64, 5, 1>(const GridView &, Ctl *,
+                                                 const Sched &, hipStream_t);
+template int blocked_blocks_per_cu<kF64, 5, 1>(bool);
+}  // namespace sor

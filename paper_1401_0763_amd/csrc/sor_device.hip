@@ -355,7 +355,7 @@ SOR_EXTERN_BLOCKED_ALL(kF16)
       const GridView &, Ctl *, const Sched &, hipStream_t);                    \
   extern template int blocked_blocks_per_cu<kF64, T, ORD>(bool);
 SOR_EXTERN_BLOCKED_ORD(1, 1) SOR_EXTERN_BLOCKED_ORD(2, 1)
-SOR_EXTERN_BLOCKED_ORD(3, 1) SOR_EXTERN_BLOCKED_ORD(4, 1)
+SOR_EXTERN_BLOCKED_ORD(3, 1) SOR_EXTERN_BLOCKED_ORD(4, 1) SOR_EXTERN_BLOCKED_ORD(5, 1)
 SOR_EXTERN_BLOCKED_ORD(1, 2) SOR_EXTERN_BLOCKED_ORD(2, 2)
 SOR_EXTERN_BLOCKED_ORD(3, 2) SOR_EXTERN_BLOCKED_ORD(4, 2)
 SOR_EXTERN_BLOCKED_ORD(5, 2) SOR_EXTERN_BLOCKED_ORD(6, 2)
@@ -370,6 +370,9 @@ static hipError_t launch_blocked_ord(int T, const GridView &v, Ctl *ctl, const S
     case 2: return launch_blocked_PT<kF64, 2, ORD>(v, ctl, sc, s);
     case 3: return launch_blocked_PT<kF64, 3, ORD>(v, ctl, sc, s);
     case 4: return launch_blocked_PT<kF64, 4, ORD>(v, ctl, sc, s);
+  }
+  if constexpr (ORD == 1) {
+    if (T == 5) return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s);
   }
   if constexpr (ORD == 2) {
     switch (T) {
@@ -389,6 +392,9 @@ static int blocked_blocks_per_cu_ord(int T, bool pois) {
     case 2: return blocked_blocks_per_cu<kF64, 2, ORD>(pois);
     case 3: return blocked_blocks_per_cu<kF64, 3, ORD>(pois);
     case 4: return blocked_blocks_per_cu<kF64, 4, ORD>(pois);
+  }
+  if constexpr (ORD == 1) {
+    if (T == 5) return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
   }
   if constexpr (ORD == 2) {
     switch (T) {

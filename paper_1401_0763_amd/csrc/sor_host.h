@@ -48,7 +48,7 @@ struct sor_ctx {
   int occ[3][sor::kTMax + 1][2] = {};                   // pass blocks per CU (lazy)
   // Blocked passes of the other orderings, by pass ordering (1 four-colour,
   // 2 Jacobi; 0 unused); seg 0: by size.
-  sor_tiling tiling_var[3] = {{0, 0}, {4, 0}, {8, 0}};
+  sor_tiling tiling_var[3] = {{0, 0}, {5, 0}, {8, 0}};
   int occ_var[3][sor::kTMax + 1][2] = {};              // their pass blocks per CU (lazy)
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
   int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)

@@ -256,7 +256,7 @@ hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
 // Jacobi (ord 2, T in 1..kTMax, FP64); the view's nstrips/nseg must match T
 // and the ordering.  ctl == nullptr runs without maxima, verdict or early
 // exit.
-constexpr int kTMaxC4 = 4;
+constexpr int kTMaxC4 = 5;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s, int ord = 0);
 bool blocked_T_supported(int T);

@@ -141,7 +141,7 @@ def test_red_black_ordering_is_solve_f64_and_errors(sor, ctx):
 BLOCKED_TILINGS = [
     (2, "four-colour", 1, 8), (2, "four-colour", 2, 14), (2, "four-colour", 3, 30),
     (2, "four-colour", 4, 48), (2, "four-colour", 4, 202), (2, "four-colour", 3, 64),
-    (2, "four-colour", 2, 1024),
+    (2, "four-colour", 2, 1024), (2, "four-colour", 5, 40), (2, "four-colour", 5, 110),
     (1, "jacobi", 1, 8), (1, "jacobi", 2, 14), (1, "jacobi", 3, 30), (1, "jacobi", 4, 48),
     (1, "jacobi", 5, 40), (1, "jacobi", 6, 202), (1, "jacobi", 7, 64), (1, "jacobi", 8, 16),
     (1, "jacobi", 8, 1024)]
@@ -165,7 +165,7 @@ def test_blocked_tilings_bitwise(sor, ctx, ordering, name, T, seg, n, with_f, it
 
 
 @pytest.mark.parametrize("ordering,name,T", [
-    (2, "four-colour", 2), (2, "four-colour", 3), (2, "four-colour", 4),
+    (2, "four-colour", 2), (2, "four-colour", 3), (2, "four-colour", 4), (2, "four-colour", 5),
     (1, "jacobi", 3), (1, "jacobi", 8)])
 @pytest.mark.parametrize("K", [1, 3, 5])
 def test_blocked_stop_inside_a_pass(sor, ctx, ordering, name, T, K):
@@ -186,7 +186,7 @@ def test_blocked_stop_inside_a_pass(sor, ctx, ordering, name, T, K):
         assert_bitwise(np.array(res.hist), ref.mhist, f"{name} blocked hist T={T} K={K}")
 
 
-@pytest.mark.parametrize("ordering,name,default_T", [(2, "four-colour", 4), (1, "jacobi", 8)])
+@pytest.mark.parametrize("ordering,name,default_T", [(2, "four-colour", 5), (1, "jacobi", 8)])
 def test_simple_and_blocked_agree(sor, ctx, ordering, name, default_T):
     """The one-iteration-per-launch kernels and the blocked passes give the
     same bits (and the oracle's)."""
@@ -206,9 +206,9 @@ def test_simple_and_blocked_agree(sor, ctx, ordering, name, default_T):
 
 
 def test_variant_tiling_validation(sor, ctx):
-    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 0)
+    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (5, 0)
     assert ctx.get_variant_tiling(sor.ORDER_JACOBI) == (8, 0)
-    for ordering, bad in [(sor.ORDER_FOUR_COLOUR, (5, 0)), (sor.ORDER_JACOBI, (9, 0))]:
+    for ordering, bad in [(sor.ORDER_FOUR_COLOUR, (6, 0)), (sor.ORDER_JACOBI, (9, 0))]:
         with pytest.raises(sor.SorError):
             ctx.set_variant_tiling(ordering, *bad)
     for bad in [(0, 7), (0, 6), (0, 1026), (-1, 0)]:
@@ -219,6 +219,6 @@ def test_variant_tiling_validation(sor, ctx):
         with pytest.raises(sor.SorError):
             ctx.set_variant_tiling(ordering, 2, 64)
     ctx.set_variant_tiling(sor.ORDER_FOUR_COLOUR, 0, 96)
-    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (4, 96)
+    assert ctx.get_variant_tiling(sor.ORDER_FOUR_COLOUR) == (5, 96)
     ctx.set_variant_tiling(sor.ORDER_JACOBI, 5, 0)
     assert ctx.get_variant_tiling(sor.ORDER_JACOBI) == (5, 0)
