@@ -383,3 +383,29 @@ def test_automatic_depth(sor):
         assert c.tiling_for(64, 4096)[0] == 6
     finally:
         c.close()
+
+
+def test_profiling_counts_working_passes(sor, ctx):
+    """Profiling times runs of passes; the launch count is the number of
+    passes that did work, and profiling changes no result."""
+    n = 200
+    g = random_small(61, n, with_f=True)
+    ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 0.0, 100, 10)
+    ctx.set_tiling(64, 7, 0)
+    ctx.set_profiling(True)
+    res, u = run_gpu(sor, ctx, g, 0.0, 100, 10, hist=False)
+    ms, launches = ctx.profile()
+    ctx.set_profiling(False)
+    assert res.passes == launches == 15          # 14 passes of 7, then one of 2
+    assert ms > 0.0
+    assert_bitwise(u, ref.u, "u with profiling")
+    # A stop inside a pass: the passes queued after it exit at once and are
+    # not counted; the re-run that rebuilds the stop iterate is not timed.
+    ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 1e-6, 100000, 3)
+    ctx.set_profiling(True)
+    res, u = run_gpu(sor, ctx, g, 1e-6, 100000, 3, hist=False)
+    ms, launches = ctx.profile()
+    ctx.set_profiling(False)
+    assert res.status == sor.OK and res.iterations == ref.iterations
+    assert launches == -(-res.iterations // 7)
+    assert_bitwise(u, ref.u, "u with profiling, stopped")
