@@ -110,7 +110,7 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * A new context reports both as 0 (chosen per solve).  Until iters_per_pass
  * is set, each plain solve uses 7 where the 7-deep pass kernel keeps two
  * wavefronts resident per SIMD for the solve's precision and problem (FP64
- * Laplace problems on gfx950), else 6; batched solves use the largest of 4,
+ * and FP32 Laplace problems on gfx950), else 6; batched solves use the largest of 4,
  * 2 and 1 not above the context's depth (6 while it is automatic).  Until
  * seg_rows is set, each plain solve picks it from the grid side, so that a
  * pass has about as many tiles as the device holds resident wavefronts of the
