@@ -114,7 +114,7 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * 2 and 1 not above the context's depth (6 while it is automatic).  Until
  * seg_rows is set, each plain solve picks it from the grid side, so that a
  * pass has about as many tiles as the device holds resident wavefronts of the
- * pass kernel (4*2*iters_per_pass..768 rows); batched solves use 64 rows
+ * pass kernel (2*2*iters_per_pass..768 rows); batched solves use 64 rows
  * below n = 512, else 192 (FP64) or 96.  An
  * autotuned entry for the grid's size class (sor_autotune for plain solves,
  * sor_autotune_batch for batched ones) takes precedence.  Results do not

@@ -88,7 +88,9 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord) {
   // Resident wavefronts, counted at most two per SIMD: passes that fit three
   // measured faster with the taller tiles of the two-per-SIMD count.
   const long long slots = (long long)std::min(occ, 8) * c->cus;
-  const int lo = 4 * gm.S, hi = 768;
+  // At least 2S rows: on grids too small to fill the device, more and shorter
+  // tiles measured faster than fewer tiles with relatively less halo.
+  const int lo = 2 * gm.S, hi = 768;
   int seg = hi;
   for (int k = 1; k <= 64; ++k) {
     const long long segs = std::max(1LL, k * slots / strips);

@@ -67,8 +67,8 @@ void mix_state_free(sor_ctx *c);
 // Segment rows chosen from the grid side for one plain solve: as many tiles
 // as the pass kernel has resident wavefront slots on the device (or a whole
 // multiple of that when a single round would need segments above 768 rows),
-// and at least 4 times the stage count (2T red-black, 3T four-colour) so the
-// halo rows stay a modest overhead.
+// and at least twice the stage count (2T red-black, 3T four-colour, T
+// Jacobi).
 int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord = 0);
 // Depth of a plain solve while the context's depth is automatic: 7 where the
 // 7-deep pass kernel keeps two wavefronts per SIMD, else 6.
