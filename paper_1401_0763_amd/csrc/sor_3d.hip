@@ -217,16 +217,25 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
 
   double v[W][kK3];
   double f[POIS ? W : 1][kK3];
+  // Every position loads (positions outside the region read the plane's
+  // first cell, off = 0, and their values are never used) and stores go
+  // through a buffer resource whose dropped offset discards them: no memory
+  // instruction sits under a per-position branch, so the compiler can count
+  // the loads in flight across steps instead of draining them at each join.
   auto load_u = [&](double (&dst)[kK3], int z) {
     const double *b = g.A + (int64_t)clampi(z, 0, n + 1) * g.plane;
 #pragma unroll
-    for (int k = 0; k < kK3; ++k) dst[k] = (valid >> k & 1u) ? b[off[k]] : 0.0;
+    for (int k = 0; k < kK3; ++k) dst[k] = b[off[k]];
   };
   auto load_f = [&](double (&dst)[kK3], int z) {
     const double *b = g.F + (int64_t)clampi(z, 0, n + 1) * g.plane;
 #pragma unroll
-    for (int k = 0; k < kK3; ++k) dst[k] = (valid >> k & 1u) ? b[off[k]] : 0.0;
+    for (int k = 0; k < kK3; ++k) dst[k] = b[off[k]];
   };
+  const unsigned plane_bytes = (unsigned)(g.plane * (int64_t)sizeof(double));   // < 2^31
+  unsigned soff[kK3];                                // store offset, or dropped
+#pragma unroll
+  for (int k = 0; k < kK3; ++k) soff[k] = (core >> k & 1u) ? (unsigned)off[k] * 8u : kDrop;
 
   // Plane zbeg + j lives in register slot (1 + j) mod W, i.e. plane zr + j
   // of step s in slot (s + 1 + j) mod W.  Before step 0: u planes
@@ -283,19 +292,25 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
           }
         }
       });
-      // Plane zr-(S-1) has had every stage: store its core.
-      if (s >= 2 * S - 2) {
+      // Plane zr-(S-1) has had every stage: store its core (the stores of
+      // the first 2S-2 steps, whose plane is not final yet, are dropped).
+      {
         constexpr int cf = ((i + 2 - S) % W + W) % W;
-        double *out = g.B + (int64_t)(zr - (S - 1)) * g.plane;
+        const unsigned drop = s >= 2 * S - 2 ? 0u : kDrop;
+        const auto out = make_rsrc(g.B + (int64_t)clampi(zr - (S - 1), 0, n + 1) * g.plane,
+                                   plane_bytes);
 #pragma unroll
-        for (int k = 0; k < kK3; ++k)
-          if (core >> k & 1u) out[off[k]] = v[cf][k];
+        for (int k = 0; k < kK3; ++k) {
+          using v2 = unsigned __attribute__((ext_vector_type(2)));
+          __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, v[cf][k]), out,
+                                                (int)(soff[k] | drop), 0, 0);
+        }
       }
       // u plane zr-S is dead: its slot takes plane zr+kD3+2.  f planes
       // zr-(S-2) .. zr+kD3 stay live; f plane zr+kD3+1 takes a free slot.
-      if (zr + kD3 + 2 <= zlast) load_u(v[(i + kD3 + 3) % W], zr + kD3 + 2);
-      if constexpr (POIS)
-        if (zr + kD3 + 1 <= zlast - 1) load_f(f[(i + kD3 + 2) % W], zr + kD3 + 1);
+      // Loads past the last plane read a clamped plane and are never used.
+      load_u(v[(i + kD3 + 3) % W], min(zr + kD3 + 2, zlast));
+      if constexpr (POIS) load_f(f[(i + kD3 + 2) % W], min(zr + kD3 + 1, zlast - 1));
     });
   }
 
