@@ -254,8 +254,11 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
   for (int sb = 0; sb < nsteps; sb += W) {
     static_for<0, W>([&](auto I) __attribute__((always_inline)) {
       constexpr int i = decltype(I)::value;
+      // Steps past the walk (the last chunk's tail) keep the plane traffic and
+      // the barrier but update nothing and store nothing, so every step
+      // issues the same memory instructions.
       const int s = sb + i;
-      if (s >= nsteps) return;                   // this and the chunk's later steps
+      const bool live = s < nsteps;
       const int zr = zbeg + s;
       {
         double *Lz = L + (s % B) * PL;
@@ -268,7 +271,8 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int st = decltype(K)::value;
         const int q = zr - st;                       // this stage's plane
-        if (s >= 2 * st && q >= 1 && q <= n && (!CLS || ((cls + q) & 1) == (st & 1))) {
+        if (live && s >= 2 * st && q >= 1 && q <= n &&
+            (!CLS || ((cls + q) & 1) == (st & 1))) {
           constexpr int cs = ((i + 1 - st) % W + W) % W;     // plane q
           constexpr int cd = ((i - st) % W + W) % W;         // q - 1
           constexpr int cu = ((i + 2 - st) % W + W) % W;     // q + 1
@@ -296,7 +300,7 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
       // the first 2S-2 steps, whose plane is not final yet, are dropped).
       {
         constexpr int cf = ((i + 2 - S) % W + W) % W;
-        const unsigned drop = s >= 2 * S - 2 ? 0u : kDrop;
+        const unsigned drop = (live && s >= 2 * S - 2) ? 0u : kDrop;
         const auto out = make_rsrc(g.B + (int64_t)clampi(zr - (S - 1), 0, n + 1) * g.plane,
                                    plane_bytes);
 #pragma unroll
