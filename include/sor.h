@@ -193,10 +193,10 @@ sor_status sor_solve_f32(sor_ctx *ctx, float *u, const float *boundary,
  *   doubles).
  * With SOR_KERNEL_BLOCKED (default) one launch applies one or two whole
  * iterations from one padded grid into a second (tiles streamed plane by
- * plane, see sor_ctx_set_tiling3d): by default two for rhs == NULL when
- * check_every is even (every check then falls at the end of a launch; an odd
- * max_iters ends with a one-iteration launch), else one.  The context holds two (n+2)^3 FP64 grids
- * plus one for rhs.  With SOR_KERNEL_SIMPLE one launch per colour works in
+ * plane, see sor_ctx_set_tiling3d): by default two when check_every is even
+ * (every check then falls at the end of a launch; an odd max_iters ends with
+ * a one-iteration launch), else one.  The context holds two (n+2)^3 FP64
+ * grids plus one for rhs.  With SOR_KERNEL_SIMPLE one launch per colour works in
  * place on one grid.  Results are bit-identical either way; out->passes
  * counts launches of the streaming kernel (iterations of the simple one).
  */
@@ -254,9 +254,9 @@ sor_status sor_ctx_get_variant_tiling(const sor_ctx *ctx, int32_t ordering, sor_
 
 /*
  * Tiling of sor_solve3d_f64's streaming kernel (not in the paper; results do
- * not depend on it).  iters_per_launch: 1, 2, or 0 for the default (2 for
- * Laplace problems when check_every is even, else 1; a 2 is honoured only
- * when check_every is even).  A tile is a core
+ * not depend on it).  iters_per_launch: 1, 2, or 0 for the default (2 when
+ * check_every is even, else 1; a 2 is honoured only when check_every is
+ * even).  A tile is a core
  * of cx x cy cells in x and y and zs planes in z, one workgroup of 256
  * threads; the workgroup holds the core plus a ring of 2 cells per
  * iteration: (cx + 4) x (cy + 4) <= 2048 positions for one iteration,

@@ -168,7 +168,11 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
   constexpr int S = Stream3<T>::S, B = Stream3<T>::B, W = Stream3<T>::W;
   constexpr int PL = Stream3<T>::P;
   if (ctl_stopped(ctl)) return;
-  __shared__ double L[B * PL];
+  // With T = 2 each plane buffer has one more slot, a sink for the writes of
+  // positions outside the region (so the half-sweeps need no per-position
+  // branch, see below).
+  constexpr int PLS = T == 2 ? PL + 1 : PL;
+  __shared__ double L[B * PLS];
   __shared__ double wmax[kT3 / 64][T];
   __shared__ int wbad[kT3 / 64];
   const int tid = threadIdx.x, n = g.n, RX = g.RX, RY = g.RY;
@@ -215,6 +219,20 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
     }
   }
 
+  // T = 2, branch-free half-sweeps: every position of the thread computes an
+  // update; one at distance 0 from the region edge or outside the region
+  // reads its neighbours around an interior position instead (nb), positions
+  // outside the region write to the sink slot PL (wr), and a position that is
+  // not active in the stage keeps its value (a select, not a branch).
+  int nb[CLS ? kK3 : 1], wr[CLS ? kK3 : 1];
+  if constexpr (CLS) {
+#pragma unroll
+    for (int k = 0; k < kK3; ++k) {
+      nb[k] = (act[0] >> k & 1u) ? pos(k) : RX + 1;
+      wr[k] = (valid >> k & 1u) ? pos(k) : PL;
+    }
+  }
+
   double v[W][kK3];
   double f[POIS ? W : 1][kK3];
   // Every position loads (positions outside the region read the plane's
@@ -233,9 +251,6 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
     for (int k = 0; k < kK3; ++k) dst[k] = b[off[k]];
   };
   const unsigned plane_bytes = (unsigned)(g.plane * (int64_t)sizeof(double));   // < 2^31
-  unsigned soff[kK3];                                // store offset, or dropped
-#pragma unroll
-  for (int k = 0; k < kK3; ++k) soff[k] = (core >> k & 1u) ? (unsigned)off[k] * 8u : kDrop;
 
   // Plane zbeg + j lives in register slot (1 + j) mod W, i.e. plane zr + j
   // of step s in slot (s + 1 + j) mod W.  Before step 0: u planes
@@ -261,7 +276,7 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
       const bool live = s < nsteps;
       const int zr = zbeg + s;
       {
-        double *Lz = L + (s % B) * PL;
+        double *Lz = L + (s % B) * PLS;
         const int c0 = (i + 1) % W;
 #pragma unroll
         for (int k = 0; k < kK3; ++k)
@@ -276,7 +291,37 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
           constexpr int cs = ((i + 1 - st) % W + W) % W;     // plane q
           constexpr int cd = ((i - st) % W + W) % W;         // q - 1
           constexpr int cu = ((i + 2 - st) % W + W) % W;     // q + 1
-          double *Lq = L + ((s - st) % B) * PL;
+          double *Lq = L + ((s - st) % B) * PLS;
+          if constexpr (CLS) {
+            // Positions in groups of four: the group's LDS reads go first, so
+            // they are in flight together (the cells a half-sweep writes are
+            // never the ones it reads, but the compiler cannot know that).
+            constexpr int G = 4;
+            static_assert(kK3 % G == 0, "whole groups");
+#pragma unroll
+            for (int g0 = 0; g0 < kK3; g0 += G) {
+              double ls[G];
+#pragma unroll
+              for (int j = 0; j < G; ++j) {
+                const int p = nb[g0 + j];
+                ls[j] = (Lq[p - 1] + Lq[p + 1]) + (Lq[p - RX] + Lq[p + RX]);
+              }
+#pragma unroll
+              for (int j = 0; j < G; ++j) {
+                const int k = g0 + j;
+                const double self = v[cs][k];
+                double sum = ls[j] + (v[cd][k] + v[cu][k]);
+                if constexpr (POIS) sum = sum + f[cs][k];
+                const double gs = SIXTH * sum;
+                const double up = __builtin_fma(omega, gs - self, self);
+                const double nu = (act[st] >> k & 1u) ? up : self;
+                v[cs][k] = nu;
+                if constexpr (st + 1 < S) Lq[wr[k]] = nu;
+                m[st >> 1] = fmax(m[st >> 1], fabs(nu - self));
+                bad = bad || !__builtin_isfinite(nu);
+              }
+            }
+          } else {
 #pragma unroll
           for (int k = 0; k < kK3; ++k) {
             if ((act[st] >> k & 1u) &&
@@ -294,6 +339,7 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
               bad = bad || !__builtin_isfinite(nu);
             }
           }
+          }
         }
       });
       // Plane zr-(S-1) has had every stage: store its core (the stores of
@@ -306,8 +352,9 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
 #pragma unroll
         for (int k = 0; k < kK3; ++k) {
           using v2 = unsigned __attribute__((ext_vector_type(2)));
+          const unsigned so = (core >> k & 1u) ? (unsigned)off[k] * 8u : kDrop;
           __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, v[cf][k]), out,
-                                                (int)(soff[k] | drop), 0, 0);
+                                                (int)(so | drop), 0, 0);
         }
       }
       // u plane zr-S is dead: its slot takes plane zr+kD3+2.  f planes

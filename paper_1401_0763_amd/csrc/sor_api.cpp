@@ -287,11 +287,11 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
 
 // Iterations per launch of a 3-D streaming solve.  Two need every check to
 // fall at the end of a two-iteration pass (check_every even; an odd max_iters
-// ends with a one-iteration pass).  By default two for Laplace problems and
-// one with a source (whose extra planes leave one wavefront per SIMD at two);
-// a context setting of 1 or 2 is honoured under the same condition.
+// ends with a one-iteration pass).  Two by default (with or without a
+// source); a context setting of 1 or 2 is honoured under the same condition.
 int iters3d_for(sor_ctx *c, int64_t check_every, bool pois) {
-  const int want = c->tiling3d[0] > 0 ? c->tiling3d[0] : (pois ? 1 : 2);
+  (void)pois;
+  const int want = c->tiling3d[0] > 0 ? c->tiling3d[0] : 2;
   return (want == 2 && check_every % 2 == 0) ? 2 : 1;
 }
 

@@ -149,6 +149,7 @@ def test_tiling3d_reporting_and_rejection(sor, ctx):
     assert T == 1 and (cx + 4) * (cy + 4) <= 2048 and 1 <= zs <= 256
     T, cx, cy, zs = ctx.tiling3d_for(256, check_every=10)
     assert T == 2 and (cx + 8) * (cy + 8) <= 2032 and 1 <= zs <= 256
+    assert ctx.tiling3d_for(256, has_rhs=True, check_every=10)[0] == 2   # with a source too
     ctx.set_tiling3d(30, 11, 5)
     assert ctx.tiling3d_for(256) == (1, 29, 11, 5)     # 9 equal strips of <= 30
     assert ctx.tiling3d_for(256, check_every=4) == (2, 29, 11, 5)
