@@ -293,10 +293,11 @@ __global__ __launch_bounds__(kT3) void sor3d_stream_kernel(Geo3 g, Ctl *ctl, Sch
           constexpr int cu = ((i + 2 - st) % W + W) % W;     // q + 1
           double *Lq = L + ((s - st) % B) * PLS;
           if constexpr (CLS) {
-            // Positions in groups of four: the group's LDS reads go first, so
-            // they are in flight together (the cells a half-sweep writes are
-            // never the ones it reads, but the compiler cannot know that).
-            constexpr int G = 4;
+            // The LDS reads of a group of positions (all eight: a group of
+            // four ran 1-2 % slower) go first, so they are in flight together
+            // (the cells a half-sweep writes are never the ones it reads, but
+            // the compiler cannot know that).
+            constexpr int G = 8;
             static_assert(kK3 % G == 0, "whole groups");
 #pragma unroll
             for (int g0 = 0; g0 < kK3; g0 += G) {
