@@ -138,7 +138,11 @@ __global__ __launch_bounds__(kX3 * kY3) void sor3d_colour_kernel(Grid3 g, Ctl *c
 // ---------------------------------------------------------------------------
 constexpr int kT3 = 256;            // threads per workgroup
 constexpr int kK3 = 8;              // positions per thread per plane
-constexpr int kD3 = 2;              // planes loaded ahead of the one first needed
+// Planes loaded ahead of the one first needed.  A step takes microseconds, so
+// the next plane's load has a step to arrive; loading more ahead only holds
+// registers (0 ran as fast as 2 on Laplace problems and 1-7 % faster with a
+// source, whose planes then leave more room).
+constexpr int kD3 = 0;
 
 template <int T>
 struct Stream3 {
