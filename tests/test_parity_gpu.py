@@ -167,6 +167,40 @@ def test_f64_nonfinite_boundary_reported(sor, ctx):
         assert res.status == sor.ENONFINITE
 
 
+@pytest.mark.parametrize("bits,n,scale,first_bad", [
+    (64, 130, 0.15, 6), (64, 130, 0.2, 3), (64, 37, 0.25, 2),
+    (32, 130, 0.15, 6), (32, 37, 0.25, 2)])
+def test_overflow_during_solve_reported(sor, ctx, bits, n, scale, first_bad):
+    """Finite inputs whose iterates overflow: with a uniform boundary near a
+    fraction of the largest finite value, over-relaxation overshoots and a
+    neighbour sum leaves the finite range after a few iterations, between two
+    checks (K = 10).  Every solve must stop with ENONFINITE by the end of the
+    pass in which the oracle finds the first infinite change, with the same
+    changes up to and including that iteration (the infinite one included)."""
+    dtype = torch.float64 if bits == 64 else torch.float32
+    top = float(np.finfo(np.float64 if bits == 64 else np.float32).max)
+    v = float(np.float32(scale * top)) if bits == 32 else scale * top
+    from workloads import Grid
+    g = Grid(n, np.zeros((n, n)), np.full(4 * n, v), None, omega_opt(n))
+    fn = oracle.sor_f64 if bits == 64 else oracle.sor_f32
+    ref = fn(g.u0, g.bdy, None, g.omega, 0.0, 100, 10, hist=True)
+    assert ref.status == oracle.ENONFINITE and ref.iterations == first_bad
+    assert math.isinf(ref.mhist[-1])
+    for T, seg in [(1, 8), (4, 64), (7, 94), (8, 16), (0, 0)]:
+        _say(f"overflow bits={bits} n={n} scale={scale} T={T} seg={seg}")
+        if T:
+            ctx.set_kernel(sor.KERNEL_BLOCKED)
+            ctx.set_tiling(bits, T, seg)
+        else:
+            ctx.set_kernel(sor.KERNEL_SIMPLE)
+        res, _ = run_gpu(sor, ctx, g, 0.0, 100, 10, dtype=dtype)
+        assert res.status == sor.ENONFINITE and not res.converged, (T, res)
+        span = T if T else 1
+        assert first_bad <= res.iterations < first_bad + span, (T, res.iterations)
+        assert_bitwise(np.array(res.hist[:first_bad]), ref.mhist,
+                       f"changes up to the overflow, T={T}")
+
+
 def test_invalid_arguments_rejected(sor, ctx):
     n = 8
     u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
