@@ -162,6 +162,28 @@ def test_tiling3d_reporting_and_rejection(sor, ctx):
     ctx.set_tiling3d(0, 0, 0)
 
 
+@pytest.mark.parametrize("n,scale,first_bad", [(41, 0.12, 3), (20, 0.15, 2)])
+def test_overflow_during_solve_reported(sor, ctx, n, scale, first_bad):
+    """Finite faces at a fraction of the largest double: over-relaxation
+    overshoots and a neighbour sum overflows a few iterations in, between two
+    checks (K = 10).  Every launch shape stops with ENONFINITE by the end of
+    the launch holding the oracle's first infinite change, with the same
+    changes up to and including it."""
+    from workloads import Grid
+    top = float(np.finfo(np.float64).max)
+    g = Grid(n, np.zeros((n, n, n)), np.full((6, n, n), scale * top), None, omega_opt(n))
+    ref = oracle.sor3d_f64(g.u0, g.bdy, None, g.omega, 0.0, 100, 10, hist=True)
+    assert ref.status == oracle.ENONFINITE and ref.iterations == first_bad
+    for t in [(0, 0, 0, 0), (1, 0, 0, 0), (2, 0, 0, 0), (2, 4, 3, 3), (1, 7, 5, 1)]:
+        _say(f"overflow 3d n={n} scale={scale} tiling={t}")
+        ctx.set_tiling3d(*t[1:], iters=t[0])
+        res, _ = run3(sor, ctx, g, 0.0, 100, 10)
+        assert res.status == sor.ENONFINITE and not res.converged, (t, res)
+        assert first_bad <= res.iterations < first_bad + 2, (t, res.iterations)
+        assert_bitwise(res.hist[:first_bad], ref.mhist, f"changes up to the overflow, {t}")
+    ctx.set_tiling3d(0, 0, 0)
+
+
 def test_nonfinite_input_and_invalid_arguments(sor, ctx):
     n = 9
     g = random_cube(5, n, with_f=True)

@@ -135,6 +135,34 @@ def test_red_black_ordering_is_solve_f64_and_errors(sor, ctx):
         assert r.status == sor.ENONFINITE, name
 
 
+@pytest.mark.parametrize("ordering,n,scale,first_bad", [
+    (1, 37, 0.3, 7), (1, 130, 0.35, 3), (2, 130, 0.15, 7), (2, 37, 0.25, 2)])
+def test_overflow_during_solve_reported(sor, ctx, ordering, n, scale, first_bad):
+    """Finite inputs whose iterates overflow between two checks (K = 10): a
+    uniform boundary at a fraction of the largest double.  Blocked passes of
+    several depths and the one-iteration kernel stop with ENONFINITE by the
+    end of the pass holding the oracle's first infinite change, with the same
+    changes up to and including it."""
+    from workloads import Grid, omega_opt
+    top = float(np.finfo(np.float64).max)
+    omega = 1.0 if ordering == 1 else omega_opt(n)
+    g = Grid(n, np.zeros((n, n)), np.full(4 * n, scale * top), None, omega)
+    ref = oracle.variant_f64(ordering, g.u0, g.bdy, None, omega, 0.0, 100, 10, hist=True)
+    assert ref.status == oracle.ENONFINITE and ref.iterations == first_bad
+    depths = (1, 3, 8) if ordering == 1 else (1, 3, 5)
+    for T in depths + (0,):
+        _say(f"overflow ordering={ordering} n={n} scale={scale} T={T}")
+        if T:
+            ctx.set_kernel(sor.KERNEL_BLOCKED)
+            ctx.set_variant_tiling(ordering, T, 0)
+        else:
+            ctx.set_kernel(sor.KERNEL_SIMPLE)
+        res, _ = run(sor, ctx, ordering, g, omega, 0.0, 100, 10)
+        assert res.status == sor.ENONFINITE and not res.converged, (T, res)
+        assert first_bad <= res.iterations < first_bad + max(T, 1), (T, res.iterations)
+        assert_bitwise(res.hist[:first_bad], ref.mhist, f"changes up to the overflow, T={T}")
+
+
 # Blocked passes of both orderings: every depth (truncated passes when fewer
 # iterations remain), segment heights that do and do not divide the grid, and
 # strips with a ragged last one.
