@@ -123,6 +123,29 @@ def test_batch_nonfinite_grid_reported(sor, ctx):
         assert res[k].status in (sor.OK, sor.NOT_CONVERGED)
 
 
+def test_batch_overflow_grid_reported(sor, ctx):
+    """A grid whose finite iterates overflow between two checks (uniform
+    boundary at 0.15 of the largest double, first infinite change at
+    iteration 6) ends with ENONFINITE; the other grids of the batch are still
+    the oracle's bit for bit."""
+    from workloads import Grid
+    n = 130
+    top = float(np.finfo(np.float64).max)
+    bad = Grid(n, np.zeros((n, n)), np.full(4 * n, 0.15 * top), None, omega_opt(n),
+               tol=0.0, max_iters=50, check_every=10)
+    ref = oracle.sor_f64(bad.u0, bad.bdy, None, bad.omega, 0.0, 50, 10)
+    assert ref.status == oracle.ENONFINITE and ref.iterations == 6
+    grids = mixed_specs(7, 6)
+    grids[2] = bad
+    _say(f"batch overflow sizes={[g.n for g in grids]}")
+    res, us = run_batch(sor, ctx, grids)
+    assert res[2].status == sor.ENONFINITE and not res[2].converged, res[2]
+    assert 6 <= res[2].iterations < 6 + 8, res[2].iterations
+    others = [k for k in range(len(grids)) if k != 2]
+    check_against_oracle([grids[k] for k in others], [res[k] for k in others],
+                         [us[k] for k in others])
+
+
 def test_autotune_returns_supported_tiling_and_keeps_results(sor, ctx):
     T, seg = ctx.autotune(64, 300)
     assert 1 <= T <= 8 and 8 <= seg <= 1024
