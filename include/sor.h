@@ -306,8 +306,11 @@ sor_status sor_residual_f64(sor_ctx *ctx, const double *u,
  *   the correction is added as u + (double)e * 2^-p.
  *   inner_iters <= 0 selects 2*n.  rel_hist: optional HOST array of
  *   max_outer + 1 doubles receiving rel before each correction and at exit.
- * Returns SOR_OK when rel <= rel_tol was reached, else SOR_NOT_CONVERGED, or
- * an error status.
+ *   With ||b||_2 = 0, rel is ||r||_2.  The norms are plain FP64 sums of
+ *   squares, so entries of r or b above about 1e150 overflow them.
+ * Returns SOR_OK when rel <= rel_tol was reached, else SOR_NOT_CONVERGED,
+ * SOR_ENONFINITE when rel is not finite (a non-finite value in the grid or
+ * an overflowing norm) or an inner sweep produced one, or an error status.
  */
 sor_status sor_solve_mixed(sor_ctx *ctx, double *u, const double *boundary,
                            const double *rhs, int32_t n, double omega,
