@@ -200,7 +200,7 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
                           float(corr_tol), int(max_outer), int(inner_bits),
                           int(inner_iters), ctypes.byref(outer), ctypes.byref(rel),
                           _ptr(rh, ctypes.c_double), ctypes.byref(corr))
-    if st < 0:
+    if st < 0 and st != ENONFINITE:
         raise ValueError(f"oracle_mixed rejected its arguments (status {st})")
     return MixedResult(u, st, outer.value, rel.value, rh[: outer.value + 1],
                        corr.value)

@@ -553,7 +553,10 @@ static int orc_scale_exp(double target, double rinf)
  * corr_tol > 0 adds a second way to stop, tested after rel: at least one
  * correction applied and the last one's max |e * 2^-p| below corr_tol (the
  * change of u over one outer step).
- * Returns ORC_OK when a stopping test passed, else ORC_NOT_CONVERGED.
+ * Returns ORC_OK when a stopping test passed, ORC_ENONFINITE when rel is not
+ * finite (a NaN or infinity in the data, or a norm that overflows; the paper
+ * says nothing of such values, and every solve here ends on them), else
+ * ORC_NOT_CONVERGED.
  */
 int oracle_mixed(int n, double *u, const double *bdy, const double *f,
                  double omega, double rel_tol, double corr_tol,
@@ -589,6 +592,7 @@ int oracle_mixed(int n, double *u, const double *bdy, const double *f,
         orc_residual_core(n, U, F, r, st);
         rel = (st[1] > 0.0) ? sqrt(st[0]) / sqrt(st[1]) : sqrt(st[0]);
         if (relhist) relhist[outer] = rel;
+        if (!isfinite(rel)) { status = ORC_ENONFINITE; break; }
         if (rel <= rel_tol || st[2] == 0.0) { status = ORC_OK; break; }
         if (corr_tol > 0.0 && outer > 0 && last_corr < corr_tol) { status = ORC_OK; break; }
         if (outer == max_outer) break;

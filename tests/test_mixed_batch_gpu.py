@@ -94,6 +94,78 @@ def test_mixed_batch_correction_stop_rule(sor, ctx):
         assert bitwise(u.cpu().numpy(), ref.u), k
 
 
+def _nonfinite_cases(n, seed):
+    """(boundary, source) pairs with no finite solution or with 2-norms that
+    overflow: a NaN in the source, an infinite boundary value, entries of
+    about 1e200."""
+    g = random_small(seed, n, with_f=True)
+    nan_f = g.f.copy()
+    nan_f[n // 2, 1] = np.nan
+    inf_b = g.bdy.copy()
+    inf_b[n + 2] = np.inf
+    return [(g.bdy, nan_f), (inf_b, g.f), (g.bdy * 1e200, None)]
+
+
+@pytest.mark.parametrize("bits", [32, 16])
+def test_mixed_nonfinite_data_reported(sor, ctx, bits):
+    """Single mixed solves and a mixed batch: data with a NaN, an infinity or
+    overflowing norms ends with ENONFINITE before any correction, as in the
+    oracle; the finite grids of the same batch are still the oracle's bit for
+    bit."""
+    n = 40
+    cases = _nonfinite_cases(n, 61)
+    for k, (b, f) in enumerate(cases):
+        ref = oracle.mixed(np.zeros((n, n)), b, f, omega_opt(n), 1e-9, 40, bits, 2 * n)
+        assert ref.status == oracle.ENONFINITE and ref.outer_steps == 0, k
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        r = sor.solve_mixed(u, dev(b), dev(f), omega_opt(n), 1e-9, 40, bits, 2 * n, ctx=ctx)
+        assert r.status == sor.ENONFINITE and r.outer_steps == 0, (k, r)
+    good = grids_for(6, [30, 57, 90])
+    grids = [(g.bdy, g.f, g.u0) for g in good] + [(b, f, np.zeros((n, n))) for b, f in cases]
+    us = [dev(u0) for _, _, u0 in grids]
+    specs = [sor.MixedSpec(u, dev(b), dev(f), None, 1e-9, 0.0, 40, 0)
+             for u, (b, f, _) in zip(us, grids)]
+    res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
+    for k, (g, r, u) in enumerate(zip(good, res, us)):
+        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), 1e-9, 40, bits, 2 * g.n)
+        assert ref.converged and r.converged, (k, r)
+        assert r.outer_steps == ref.outer_steps
+        assert bitwise(u.cpu().numpy(), ref.u), k
+    for k in range(len(good), len(grids)):
+        assert res[k].status == sor.ENONFINITE and res[k].outer_steps == 0, (k, res[k])
+
+
+def test_server_nonfinite_request_reported(sor):
+    """A request with non-finite data completes with ENONFINITE; the requests
+    around it still equal the oracle's standalone solves bit for bit."""
+    n = 40
+    cases = _nonfinite_cases(n, 62)
+    good = [random_small(700 + k, m, with_f=True) for k, m in enumerate([24, 50, 33])]
+    reqs = [(g.bdy, g.f) for g in good[:2]] + cases + [(good[2].bdy, good[2].f)]
+    srv = sor.Server(0, inner_bits=32, hbm_budget=24 << 20, max_slots=3, slice_ms=0.3)
+    try:
+        tickets = [srv.submit(b, f, None, 0.0, 1e-9, 0.0, 40, 0) for b, f in reqs]
+        done = {}
+        t_end = time.time() + 120
+        while len(done) < len(tickets) and time.time() < t_end:
+            for t in tickets:
+                if t not in done:
+                    c = srv.poll(t, wait_ms=5.0)
+                    if c is not None:
+                        done[t] = c
+        assert len(done) == len(tickets), srv.stats()
+    finally:
+        srv.close()
+    for k in range(2, 2 + len(cases)):
+        assert done[tickets[k]].status == sor.ENONFINITE, (k, done[tickets[k]].result)
+    for t, g in zip([tickets[0], tickets[1], tickets[-1]], good):
+        c = done[t]
+        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), 1e-9, 40, 32,
+                           2 * g.n)
+        assert c.status == sor.OK and ref.converged, (g.n, c.result)
+        assert bitwise(c.u, ref.u), g.n
+
+
 @pytest.mark.parametrize("bits", [32, 16])
 def test_server_results_equal_standalone(sor, bits):
     """A stream of requests through a small server (few slots, small memory

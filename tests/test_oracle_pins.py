@@ -360,6 +360,29 @@ def test_invalid_arguments_and_nonfinite():
     assert res.status == oracle.ENONFINITE
 
 
+@pytest.mark.parametrize("bits", [32, 16])
+def test_mixed_nonfinite_data_never_converges(bits):
+    """A NaN in the source or an infinite boundary value has no solution, and
+    entries of about 1e200 overflow the 2-norms the stopping rule uses: each
+    ends the mixed solve with ENONFINITE before any correction.  (A NaN that
+    spreads through the grid drops out of the max |r| comparisons, so max |r|
+    alone would read as zero, i.e. as an exact solution.)"""
+    n = 9
+    rng = np.random.default_rng(5)
+    bdy = rng.uniform(0.0, 1.0, 4 * n)
+    f = rng.standard_normal((n, n))
+    nan_f = f.copy()
+    nan_f[4, 2] = np.nan
+    inf_b = bdy.copy()
+    inf_b[n + 3] = np.inf
+    for b, ff in ((bdy, nan_f), (inf_b, f), (bdy * 1e200, None)):
+        res = oracle.mixed(np.zeros((n, n)), b, ff, 1.5, 1e-10, 5, bits, 2 * n)
+        assert res.status == oracle.ENONFINITE and res.outer_steps == 0
+        assert not math.isfinite(res.rel_residual)
+    res = oracle.mixed(np.zeros((n, n)), bdy * 1e100, f, 1.5, 1e-10, 40, bits, 4 * n)
+    assert res.status == oracle.OK and math.isfinite(res.rel_residual)
+
+
 # ---------------------------------------------------------------------------
 # Residual
 # ---------------------------------------------------------------------------
