@@ -182,6 +182,12 @@ def test_overflow_during_solve_reported(sor, ctx, n, scale, first_bad):
         assert first_bad <= res.iterations < first_bad + 2, (t, res.iterations)
         assert_bitwise(res.hist[:first_bad], ref.mhist, f"changes up to the overflow, {t}")
     ctx.set_tiling3d(0, 0, 0)
+    _say(f"overflow 3d n={n} scale={scale} colour kernel")
+    ctx.set_kernel(sor.KERNEL_SIMPLE)
+    res, _ = run3(sor, ctx, g, 0.0, 100, 10)
+    ctx.set_kernel(sor.KERNEL_BLOCKED)
+    assert res.status == sor.ENONFINITE and res.iterations == first_bad, res
+    assert_bitwise(res.hist[:first_bad], ref.mhist, "changes up to the overflow, colour kernel")
 
 
 def test_nonfinite_input_and_invalid_arguments(sor, ctx):
