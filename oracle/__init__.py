@@ -63,7 +63,8 @@ def _load():
     lib.oracle_residual_f64.restype = ctypes.c_int
     lib.oracle_mixed.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_int64,
-                                 ctypes.c_int, ctypes.c_int64, i64p, dp, dp, dp]
+                                 ctypes.c_int, ctypes.c_int64, ctypes.c_int, i64p, dp,
+                                 dp, dp]
     lib.oracle_mixed.restype = ctypes.c_int
     lib.oracle_sor3d_f64.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int64,
@@ -184,8 +185,9 @@ class MixedResult:
 
 
 def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
-          inner_iters=None, corr_tol=0.0) -> MixedResult:
-    """FP64 defect correction around reduced-precision red-black SOR."""
+          inner_iters=None, corr_tol=0.0, threads=1) -> MixedResult:
+    """FP64 defect correction around reduced-precision red-black SOR
+    (threads > 1: inner half-sweeps on that many OpenMP workers, same result)."""
     lib = _load()
     n = int(np.asarray(bdy).size // 4)
     if inner_iters is None:
@@ -198,7 +200,8 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
     st = lib.oracle_mixed(n, _ptr(u, ctypes.c_double), _ptr(b, ctypes.c_double),
                           _ptr(ff, ctypes.c_double), float(omega), float(rel_tol),
                           float(corr_tol), int(max_outer), int(inner_bits),
-                          int(inner_iters), ctypes.byref(outer), ctypes.byref(rel),
+                          int(inner_iters), int(threads), ctypes.byref(outer),
+                          ctypes.byref(rel),
                           _ptr(rh, ctypes.c_double), ctypes.byref(corr))
     if st < 0 and st != ENONFINITE:
         raise ValueError(f"oracle_mixed rejected its arguments (status {st})")

@@ -432,13 +432,15 @@ static float *orc_make_F32(int n, const float *f)
     return F;
 }
 
-/* One float half-sweep of one colour; half_store != 0 rounds every stored
- * value to binary16 (storage in half precision, arithmetic in float). */
-static float orc_half_sweep_f32(int n, float *U, const float *F, float w,
-                                int colour, int half_store, int *bad)
+/* One float half-sweep of one colour over rows i_lo..i_hi; half_store != 0
+ * rounds every stored value to binary16 (storage in half precision,
+ * arithmetic in float). */
+static float orc_half_sweep_rows_f32(int n, float *U, const float *F, float w,
+                                     int colour, int half_store, int i_lo, int i_hi,
+                                     int *bad)
 {
     float m = 0.0f;
-    for (int i = 1; i <= n; ++i) {
+    for (int i = i_lo; i <= i_hi; ++i) {
         int j0 = 1 + ((i + 1 + colour) & 1);
         for (int j = j0; j <= n; j += 2) {
             float old = U[AT(i, j)];
@@ -456,6 +458,27 @@ static float orc_half_sweep_f32(int n, float *U, const float *F, float w,
             U[AT(i, j)] = nu;
         }
     }
+    return m;
+}
+
+/* The same half-sweep over every row; threads > 1 splits the rows across
+ * that many OpenMP workers (a colour's cells are independent and max is
+ * exact, so the result does not depend on the thread count). */
+static float orc_half_sweep_f32(int n, float *U, const float *F, float w,
+                                int colour, int half_store, int threads, int *bad)
+{
+    if (threads <= 1)
+        return orc_half_sweep_rows_f32(n, U, F, w, colour, half_store, 1, n, bad);
+    float m = 0.0f;
+    int badc = 0;
+#pragma omp parallel for num_threads(threads) schedule(static) reduction(max : m) reduction(| : badc)
+    for (int i = 1; i <= n; ++i) {
+        int b1 = 0;
+        float r = orc_half_sweep_rows_f32(n, U, F, w, colour, half_store, i, i, &b1);
+        if (r > m) m = r;
+        badc |= b1;
+    }
+    if (badc) *bad = 1;
     return m;
 }
 
@@ -494,8 +517,8 @@ int oracle_sor_f32(int n, float *u, const float *bdy, const float *f,
     double last = NAN;
     for (it = 1; it <= max_iters; ++it) {
         int bad = 0;
-        float m0 = orc_half_sweep_f32(n, U, F, w, 0, 0, &bad);
-        float m1 = orc_half_sweep_f32(n, U, F, w, 1, 0, &bad);
+        float m0 = orc_half_sweep_f32(n, U, F, w, 0, 0, 1, &bad);
+        float m1 = orc_half_sweep_f32(n, U, F, w, 1, 0, 1, &bad);
         double m = (double)(m1 > m0 ? m1 : m0);
         if (mhist) mhist[it - 1] = m;
         if (bad) { status = ORC_ENONFINITE; last = m; break; }
@@ -553,6 +576,9 @@ static int orc_scale_exp(double target, double rinf)
  * corr_tol > 0 adds a second way to stop, tested after rel: at least one
  * correction applied and the last one's max |e * 2^-p| below corr_tol (the
  * change of u over one outer step).
+ * threads > 1 runs each inner half-sweep on that many OpenMP workers (the
+ * residual, its sums and the accumulation stay serial, in row-major order);
+ * results are identical for every thread count.
  * Returns ORC_OK when a stopping test passed, ORC_ENONFINITE when rel is not
  * finite (a NaN or infinity in the data, or a norm that overflows; the paper
  * says nothing of such values, and every solve here ends on them), else
@@ -561,11 +587,11 @@ static int orc_scale_exp(double target, double rinf)
 int oracle_mixed(int n, double *u, const double *bdy, const double *f,
                  double omega, double rel_tol, double corr_tol,
                  int64_t max_outer, int inner_bits, int64_t inner_iters,
-                 int64_t *outer_out, double *rel_out, double *relhist,
+                 int threads, int64_t *outer_out, double *rel_out, double *relhist,
                  double *corr_out)
 {
     if (n < 1 || !u || !bdy || !(omega > 0.0 && omega < 2.0) ||
-        !(rel_tol >= 0.0) || max_outer < 0 || inner_iters < 0 ||
+        !(rel_tol >= 0.0) || max_outer < 0 || inner_iters < 0 || threads < 1 ||
         (inner_bits != 32 && inner_bits != 16))
         return ORC_EINVAL;
     size_t cells = (size_t)(n + 2) * (size_t)(n + 2);
@@ -605,8 +631,8 @@ int oracle_mixed(int n, double *u, const double *bdy, const double *f,
         memset(E, 0, sizeof(float) * cells);
         for (int64_t k = 0; k < inner_iters; ++k) {
             int bad = 0;
-            orc_half_sweep_f32(n, E, R, w, 0, half, &bad);
-            orc_half_sweep_f32(n, E, R, w, 1, half, &bad);
+            orc_half_sweep_f32(n, E, R, w, 0, half, threads, &bad);
+            orc_half_sweep_f32(n, E, R, w, 1, half, threads, &bad);
         }
         double inv = ldexp(1.0, -p);
         last_corr = 0.0;

@@ -448,3 +448,69 @@ def test_mixed_precision_refinement_reaches_fp64_accuracy(bits, tol):
     assert np.max(np.abs(res.u - ref)) <= 1e-9 * np.max(np.abs(ref))
     # cross-check the returned rel against the residual routine
     assert abs(oracle.rel_residual(res.u, bdy, f) - res.rel_residual) <= 1e-3 * tol
+
+
+@pytest.mark.parametrize("bits", [32, 16])
+def test_mixed_correction_size_stop_rule(bits):
+    """The second stopping rule of the mixed solve: after at least one
+    correction, stop when the last correction's largest magnitude is below
+    corr_tol.  The corrections are measured here from the iterates themselves
+    (u_k - u_{k-1}, from runs limited to k and k-1 corrections), not from the
+    oracle's own report: the first one exactly (u_0 = 0, so u_1 is the
+    correction), later ones to within a rounding of u.  A rule tested before
+    the correction is added, or on the scaled correction (without 2^-p), or
+    allowed before any correction, fails here."""
+    n = 21
+    rng = np.random.default_rng(16)
+    bdy = rng.uniform(0.0, 100.0, 4 * n)
+    f = rng.standard_normal((n, n)) * 50.0
+    omega = omega_opt(n)
+    inner = 6                      # weak inner solves: corrections shrink slowly
+    K = 7
+    us = [np.zeros((n, n))]
+    for k in range(1, K + 1):
+        r = oracle.mixed(np.zeros((n, n)), bdy, f, omega, 0.0, k, bits, inner)
+        assert r.outer_steps == k and r.status == oracle.NOT_CONVERGED
+        us.append(r.u)
+    c = [None] + [float(np.max(np.abs(us[k] - us[k - 1]))) for k in range(1, K + 1)]
+    assert all(c[k + 1] < c[k] * 0.9 for k in range(1, K)), c   # strictly shrinking
+    run = lambda tol: oracle.mixed(np.zeros((n, n)), bdy, f, omega, 0.0, K + 3, bits,
+                                   inner, corr_tol=tol)
+    # The first correction is u_1 exactly: its size is the returned one.
+    r1 = run(c[1] * (1 + 1e-9))
+    assert r1.status == oracle.OK and r1.outer_steps == 1
+    assert r1.last_correction == c[1]
+    np.testing.assert_array_equal(r1.u, us[1])
+    assert run(c[1]).outer_steps == 2           # strict: c_1 < c_1 is false
+    # A threshold just above (below) c_j stops after j (j + 1) corrections,
+    # returning the iterate that includes the last correction.
+    for j in range(2, K):
+        hi, lo = run(c[j] * (1 + 1e-6)), run(c[j] * (1 - 1e-6))
+        assert hi.status == oracle.OK and hi.outer_steps == j, (j, hi.outer_steps)
+        assert lo.status == oracle.OK and lo.outer_steps == j + 1, (j, lo.outer_steps)
+        np.testing.assert_array_equal(hi.u, us[j])
+        np.testing.assert_array_equal(lo.u, us[j + 1])
+        assert abs(hi.last_correction - c[j]) <= 1e-9 * c[j]
+    # A huge corr_tol still applies one correction first; max_outer = 0
+    # applies none and the rule never fires.
+    big = run(1e300)
+    assert big.outer_steps == 1 and big.status == oracle.OK
+    r0 = oracle.mixed(np.zeros((n, n)), bdy, f, omega, 0.0, 0, bits, inner, corr_tol=1e300)
+    assert r0.outer_steps == 0 and r0.status == oracle.NOT_CONVERGED
+    # The residual rule is tested first: with rel_tol above the starting
+    # residual no correction is applied at all.
+    r_rel = oracle.mixed(np.zeros((n, n)), bdy, f, omega, 2.0, K, bits, inner, corr_tol=1e300)
+    assert r_rel.outer_steps == 0 and r_rel.status == oracle.OK
+
+
+def test_mixed_threads_bitwise_equal_serial():
+    n = 37
+    rng = np.random.default_rng(17)
+    bdy = rng.uniform(0.0, 100.0, 4 * n)
+    f = rng.standard_normal((n, n))
+    for bits in (32, 16):
+        a = oracle.mixed(np.zeros((n, n)), bdy, f, omega_opt(n), 0.0, 3, bits, 2 * n)
+        b = oracle.mixed(np.zeros((n, n)), bdy, f, omega_opt(n), 0.0, 3, bits, 2 * n,
+                         threads=4)
+        np.testing.assert_array_equal(a.u.view(np.uint64), b.u.view(np.uint64))
+        np.testing.assert_array_equal(a.relhist, b.relhist)
