@@ -12,15 +12,19 @@ passes with device-side stopping checks, unpack).
 Output: one JSON line with GLUP/s (giga lattice-site updates per second), the
 dominant kernel's roofline position, and the CPU oracle's rate on the host
 cores.  The sweep applies 7 iterations per pass over HBM, so HBM traffic is
-a fraction of the algorithmic bytes: the roofline reports algorithmic FP64
-operations per lattice update (9: three adds for the neighbour sum, the
-quarter, the difference, the relaxation product, the update, the change and
-its running maximum) over the HIP-event-timed kernel time, against the
-non-fused FP64 vector rate (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz), with the
-HBM-equivalent bandwidth (16 algorithmic bytes per update), the
-counter-measured traffic and the achievable bandwidth of a 1 GiB device copy
-beside it.  The CPU baseline is the oracle on up to 16 host threads, with its
-single-thread rate and the CPU model beside it.
+a fraction of the algorithmic bytes: the roofline reports the update's FP64
+floating-point operations (9 per lattice update, a fused multiply-add
+counting two: three adds for the neighbour sum, the quarter-difference and
+the relaxation step as two fused multiply-adds, the change and its running
+maximum) over the HIP-event-timed kernel time, against the chip's FP64
+vector peak of 78.6 TFLOP/s (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4
+GHz).  Beside it: the same work in issue slots (7 FP64 vector instructions
+per update against 39.3 T instructions/s), the HBM-equivalent bandwidth (16
+algorithmic bytes per update), the counter-measured HBM traffic per launch
+with its bandwidth and fraction of the 8 TB/s peak, and the achievable
+bandwidth of a 1 GiB device copy.  Every timed step starts from the zero
+interior of the workload.  The CPU baseline is the oracle on up to 16 host
+threads, with its single-thread rate and the CPU model beside it.
 Under "forms" the same line reports:
   tol      the benchmark grid solved to max |du| < 1e-8 (checked every 10);
   paper    the paper's own configuration (omega 0.376, north edge 1, other
@@ -56,8 +60,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, AMD published peak
-FP64_VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # non-fused FP64 ops, 39.3
-OPS_PER_LUP_F64 = 9            # FP64 vector operations per lattice update
+FP64_VALU_PEAK_TFLOPS = 78.6   # MI355X FP64 vector peak (fused multiply-add = 2 flops)
+FP64_VALU_ISSUE_TIPS = 256 * 4 * 16 * 2.4e9 / 1e12   # FP64 vector instructions/s, 39.3 T
+FLOPS_PER_LUP_F64 = 9          # 3 adds + 2 fused multiply-adds (2 each) + change + max
+INSTR_PER_LUP_F64 = 7          # the same as FP64 vector instructions
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "blocked_pass_f64_4096.traffic.json")
 KERNEL_SOURCES = ("paper_1401_0763_amd/csrc/sor_kernels.h",
                   "paper_1401_0763_amd/csrc/sor_internal.h",
@@ -558,8 +564,7 @@ def form_serving(sor, ctx, torch, count, burst):
         u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
         b = torch.tensor(bdy, dtype=torch.float64, device="cuda")
         ff = torch.tensor(f, dtype=torch.float64, device="cuda")
-        its, rel = fp64_to_residual(sor, ctx, u, b, ff,
-                                    2.0 / (1.0 + math.sin(math.pi / (n + 1))), tol,
+        its, rel = fp64_to_residual(sor, ctx, u, b, ff, sor.omega_opt(n), tol,
                                     max(200, n), 40 * n)
         _ = u.cpu()
         lat0.append(time.perf_counter() - t0 - stream.arrivals[k])
@@ -618,6 +623,7 @@ def main():
           file=sys.stderr, flush=True)
 
     def step():
+        u.zero_()                     # the workload's interior starts at 0
         return sor.solve_f64(u, bdy, None, g.omega, 0.0, iters, K, ctx=ctx)
 
     if args.copy_probe_mib:
@@ -647,8 +653,11 @@ def main():
     glups = n * n * iters * args.steps / dt / 1e9
     avg_launch_s = kern_ms / 1e3 / launches
     lups = float(n) * n * iters * args.steps          # in the timed kernels
-    achieved = OPS_PER_LUP_F64 * lups / (kern_ms / 1e3) / 1e12
+    achieved = FLOPS_PER_LUP_F64 * lups / (kern_ms / 1e3) / 1e12
+    issue = INSTR_PER_LUP_F64 * lups / (kern_ms / 1e3) / 1e12
     alg_bytes = BYTES_PER_LUP_F64 * n * n * T         # one full-depth pass
+    traffic = measured_traffic(n, T, seg)
+    hbm_meas = None if traffic is None else traffic / avg_launch_s / 1e9
     line = {
         "metric": "GLUP/s, 4096^2 FP64 red-black SOR (Laplace, random Dirichlet "
                   "boundary, omega_opt, 1000 iterations checked every 10)",
@@ -667,13 +676,19 @@ def main():
                    "n": n, "iterations": iters, "check_every": K,
                    "iters_per_pass": T, "seg_rows": seg},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
-                     "peak": round(FP64_VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(achieved / FP64_VALU_PEAK_TOPS, 4),
-                     "traffic": measured_traffic(n, T, seg),
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                     "traffic": traffic,
                      "kernel": f"blocked_pass_kernel<f64,T={T},laplace>",
                      "avg_launch_us": round(avg_launch_s * 1e6, 2),
                      "launches": launches,
-                     "alg_ops_per_launch": OPS_PER_LUP_F64 * n * n * T,
+                     "alg_flops_per_launch": FLOPS_PER_LUP_F64 * n * n * T,
+                     "valu_issue_Tinstr_s": round(issue, 3),
+                     "valu_issue_peak_Tinstr_s": round(FP64_VALU_ISSUE_TIPS, 2),
+                     "valu_issue_frac": round(issue / FP64_VALU_ISSUE_TIPS, 4),
+                     "hbm_measured_GBs": None if hbm_meas is None else round(hbm_meas, 1),
+                     "hbm_measured_frac": None if hbm_meas is None else
+                     round(hbm_meas / HBM_PEAK_GBS, 4),
                      "hbm_equiv_GBs": round(BYTES_PER_LUP_F64 * lups / (kern_ms / 1e3) / 1e9, 1),
                      "hbm_peak_GBs": HBM_PEAK_GBS,
                      "alg_bytes_per_launch": alg_bytes},

@@ -82,6 +82,14 @@ typedef struct sor_result {
 /* Library version string, e.g. "sor 0.1.0 gfx950". */
 const char *sor_version(void);
 
+/* Young's optimal relaxation factor for the red-black ordering of the 5-point
+ * (and 7-point) Dirichlet Laplacian with n interior nodes per side:
+ * 2 / (1 + sin(pi h)), h = 1/(n+1), i.e. 2/(1 + sqrt(1 - mu^2)) with the
+ * Jacobi spectral radius mu = cos(pi h).  Not in the paper (Sec. 2.1 runs a
+ * fixed omega); the solves and the request server use it where the caller
+ * passes no omega.  Returns NaN for n < 1.  Host-only, no device access. */
+double sor_omega_opt(int32_t n);
+
 /* Create a context bound to HIP device `device`.  Returns SOR_OK and *out, or
  * SOR_EINVAL (bad device / NULL out) or SOR_EDEVICE. */
 sor_status sor_ctx_create(int device, sor_ctx **out);

@@ -99,6 +99,8 @@ def _declare(lib):
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.sor_version.restype = ctypes.c_char_p
     lib.sor_version.argtypes = []
+    lib.sor_omega_opt.restype = ctypes.c_double
+    lib.sor_omega_opt.argtypes = [ctypes.c_int32]
     lib.sor_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
     lib.sor_ctx_create.restype = ctypes.c_int
     lib.sor_ctx_destroy.argtypes = [P]
@@ -183,6 +185,11 @@ def load_library():
 
 def version() -> str:
     return load_library().sor_version().decode()
+
+
+def omega_opt(n: int) -> float:
+    """Young's optimal relaxation factor for side n (sor_omega_opt)."""
+    return load_library().sor_omega_opt(int(n))
 
 
 class Context:
@@ -365,7 +372,7 @@ def batch_solve_f64(specs, ctx: Context | None = None) -> list[Result]:
         d.boundary = _check_tensor("boundary", sp.boundary, torch.float64, (4 * n,))
         d.rhs = None if sp.rhs is None else _check_tensor("rhs", sp.rhs, torch.float64, (n, n))
         d.n = n
-        d.omega = (2.0 / (1.0 + math.sin(math.pi / (n + 1)))) if sp.omega is None else sp.omega
+        d.omega = omega_opt(n) if sp.omega is None else sp.omega
         d.tol = sp.tol
         d.max_iters = sp.max_iters
         d.check_every = sp.check_every
@@ -399,7 +406,7 @@ def solve_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
     import torch
     n = u.shape[0]
     if omega is None:
-        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+        omega = omega_opt(n)
     ctx = ctx or context(u.device.index)
     return _solve_plain(ctx.lib.sor_solve_f64, torch.float64, u, boundary, rhs,
                         omega, tol, max_iters, check_every, hist, ctx)
@@ -411,7 +418,7 @@ def solve_f32(u, boundary, rhs=None, omega=None, tol=1e-5, max_iters=100000,
     import torch
     n = u.shape[0]
     if omega is None:
-        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+        omega = omega_opt(n)
     ctx = ctx or context(u.device.index)
     return _solve_plain(ctx.lib.sor_solve_f32, torch.float32, u, boundary, rhs,
                         omega, tol, max_iters, check_every, hist, ctx)
@@ -428,7 +435,7 @@ def solve_variant_f64(ordering, u, boundary, rhs=None, omega=None, tol=1e-8,
     import torch
     n = u.shape[0]
     if omega is None:
-        omega = 1.0 if ordering == ORDER_JACOBI else 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+        omega = 1.0 if ordering == ORDER_JACOBI else omega_opt(n)
     pu = _check_tensor("u", u, torch.float64, (n, n))
     pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
     pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
@@ -453,7 +460,7 @@ def solve3d_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
     import torch
     n = u.shape[0]
     if omega is None:
-        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+        omega = omega_opt(n)
     pu = _check_tensor("u", u, torch.float64, (n, n, n))
     pb = _check_tensor("boundary", boundary, torch.float64, (6, n, n))
     pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n, n))
@@ -491,7 +498,7 @@ def solve_mixed(u, boundary, rhs=None, omega=None, rel_tol=1e-10, max_outer=50,
     import torch
     n = u.shape[0]
     if omega is None:
-        omega = 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+        omega = omega_opt(n)
     pu = _check_tensor("u", u, torch.float64, (n, n))
     pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
     pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
@@ -535,7 +542,7 @@ def batch_solve_mixed(specs, inner_bits=32, ctx: Context | None = None) -> list[
         d.boundary = _check_tensor("boundary", sp.boundary, torch.float64, (4 * n,))
         d.rhs = None if sp.rhs is None else _check_tensor("rhs", sp.rhs, torch.float64, (n, n))
         d.n = n
-        d.omega = (2.0 / (1.0 + math.sin(math.pi / (n + 1)))) if sp.omega is None else sp.omega
+        d.omega = omega_opt(n) if sp.omega is None else sp.omega
         d.rel_tol = sp.rel_tol
         d.corr_tol = sp.corr_tol
         d.max_outer = sp.max_outer

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <new>
 #include <cmath>
 #include <cstdarg>
@@ -90,6 +91,11 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
 
 int prec_index(int bits) { return bits == 64 ? kF64 : bits == 32 ? kF32 : bits == 16 ? kF16 : -1; }
 
+double omega_opt(int n) {
+  if (n < 1) return NAN;
+  return 2.0 / (1.0 + std::sin(M_PI / ((double)n + 1.0)));
+}
+
 }  // namespace sor
 
 namespace {
@@ -132,6 +138,8 @@ GridView view_for(const GridView &base, int prec, int T, int ord = 0) {
   return v;
 }
 
+constexpr int kMaxChunk = 64;     // passes enqueued between two host checks
+
 struct PassRec {
   const void *in;
   void *out;
@@ -173,8 +181,7 @@ sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
 sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       const void *F, double omega, const Sched &sc,
                       hipStream_t s, sor_result *res, double *hist,
-                      void **result_grid, int ord = 0) {
-  Ctl *ctl = (Ctl *)c->bufs[kCtlBuf].p;
+                      void **result_grid, int ord, Ctl *ctl) {
   HIP_TRY(c, launch_ctl_reset(ctl, s));
   const sor_tiling tl = ord ? variant_tiling(c, ord, L.n, F != nullptr)
                             : tuned_tiling(c, prec, L.n, F != nullptr);
@@ -182,7 +189,8 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 
-  std::vector<PassRec> recs;
+  PassRec recs[kMaxChunk];          // the passes of the running chunk
+  int nrecs = 0;
   long long done = 0;               // iterations enqueued
   long long chunk = 1;              // passes per chunk
   void *cur = A, *oth = B;
@@ -193,7 +201,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   res->final_max_delta = NAN;
   for (;;) {
     const long long chunk_it0 = done;
-    recs.clear();
+    nrecs = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->prof) {
       sor_status pst = prof_events(c, 0, &e0, &e1);
@@ -215,7 +223,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord));
         std::swap(cur, oth);
       }
-      recs.push_back({v.in, v.out, done, Tp});
+      recs[nrecs++] = PassRec{v.in, v.out, done, Tp};
       done += Tp;
       if (done - chunk_it0 >= kHistCap - kTMax) break;
     }
@@ -226,8 +234,8 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
     const long long hist_end = h.stop ? h.stop_iter : done;
     if (c->prof) {
       long long worked = 0;                 // passes of the chunk that did not exit early
-      for (const PassRec &r : recs)
-        if (!(h.stop && r.it0 >= h.stop_iter)) ++worked;
+      for (int k = 0; k < nrecs; ++k)
+        if (!(h.stop && recs[k].it0 >= h.stop_iter)) ++worked;
       float ms = 0.f;
       HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
       c->prof_ms += ms;
@@ -243,8 +251,11 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       res->passes = h.passes_done + reruns;
       // Locate the pass in which the rule was met.
       const PassRec *pr = nullptr;
-      for (const PassRec &r : recs)
-        if (h.stop_iter > r.it0 && h.stop_iter <= r.it0 + r.T) { pr = &r; break; }
+      for (int k = 0; k < nrecs; ++k)
+        if (h.stop_iter > recs[k].it0 && h.stop_iter <= recs[k].it0 + recs[k].T) {
+          pr = &recs[k];
+          break;
+        }
       if (!pr) return fail(c, SOR_EDEVICE, "stop iteration %lld outside the chunk", h.stop_iter);
       if (h.stop == 2) {
         *result_grid = pr->out;
@@ -255,7 +266,15 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
         *result_grid = pr->out;
       } else {
         // Rule met inside the pass: redo its first iterations from its intact
-        // input, ping-ponging between the pass's two grids.
+        // input, ping-ponging between the pass's two grids.  When the pass
+        // also made a non-finite value, the re-run reports its own (a control
+        // block whose rule never passes): if one appears within the
+        // iterations up to the stop, the solve ends as non-finite instead.
+        const bool tentative = h.stop_tentative != 0;
+        const long long stop_iter = h.stop_iter;   // h is overwritten below
+        Ctl *rctl = tentative ? ctl + 1 : nullptr;
+        const Sched rsc{LLONG_MAX, 1, -1.0};
+        if (tentative) HIP_TRY(c, launch_ctl_reset(rctl, s));
         void *src = const_cast<void *>(pr->in);
         void *dst = pr->out;
         long long left = h.stop_iter - pr->it0;
@@ -264,13 +283,22 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
           GridView v = view_for(base, prec, t, ord);
           v.in = src;
           v.out = dst;
-          HIP_TRY(c, launch_blocked_pass(prec, t, v, nullptr, sc, s, ord));
+          HIP_TRY(c, launch_blocked_pass(prec, t, v, rctl, tentative ? rsc : sc, s, ord));
           ++reruns;
           *result_grid = dst;
           std::swap(src, dst);
           left -= t;
         }
         res->passes = h.passes_done + reruns;
+        if (tentative) {
+          HIP_TRY(c, hipMemcpyAsync(c->host_ctl, rctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+          HIP_TRY(c, hipStreamSynchronize(s));
+          if (c->host_ctl->stop == 2) {
+            res->converged = 0;
+            return fail(c, SOR_ENONFINITE, "non-finite value in the grid by iteration %lld",
+                        stop_iter);
+          }
+        }
       }
       return SOR_OK;
     }
@@ -281,7 +309,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       *result_grid = cur;
       return SOR_NOT_CONVERGED;
     }
-    chunk = std::min<long long>(chunk * 2, 64);
+    chunk = std::min<long long>(chunk * 2, kMaxChunk);
   }
 }
 
@@ -378,7 +406,7 @@ sor_status run_iteration_loop(sor_ctx *c, const Sched &sc, hipStream_t s, sor_re
       res->final_max_delta = h.last_max;
       return SOR_NOT_CONVERGED;
     }
-    chunk = std::min<long long>(chunk * 2, 64);
+    chunk = std::min<long long>(chunk * 2, kMaxChunk);
   }
 }
 
@@ -404,12 +432,6 @@ sor_status run_iterations3d(sor_ctx *c, double *A, double *B, const double *F, i
   return st;
 }
 
-sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K) {
-  if (!(tol >= 0.0)) return fail(c, SOR_EINVAL, "tol = %g must be >= 0", tol);
-  if (max_iters < 1) return fail(c, SOR_EINVAL, "max_iters must be >= 1");
-  if (K < 1) return fail(c, SOR_EINVAL, "check_every must be >= 1");
-  return SOR_OK;
-}
 
 template <typename T>
 sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
@@ -419,7 +441,6 @@ sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
   if (st != SOR_OK) return st;
   if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
   if ((st = check_sched(c, tol, max_iters, K)) != SOR_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
   const Layout L = make_layout(n, prec);
   const size_t bytes = (size_t)L.elems() * sizeof(T);
   const BufRole ra = prec == kF64 ? kGridA64 : kGridA32;
@@ -429,14 +450,36 @@ sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
   if (rhs && (st = ensure(c, rf, bytes))) return st;
   T *A = origin<T>(c, ra, L), *B = origin<T>(c, rb, L);
   T *F = rhs ? origin<T>(c, rf, L) : nullptr;
-  unsigned *bad = &((Ctl *)c->bufs[kCtlBuf].p)->input_nonfinite;
+  return solve_plain_on(c, prec, L, (void *)u, bdy, rhs, A, B, F, (Ctl *)c->bufs[kCtlBuf].p,
+                        omega, Sched{max_iters, K, tol}, (hipStream_t)stream, out, hist);
+}
+
+}  // namespace
+
+namespace sor {
+
+sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K) {
+  if (!(tol >= 0.0)) return fail(c, SOR_EINVAL, "tol = %g must be >= 0", tol);
+  if (max_iters < 1) return fail(c, SOR_EINVAL, "max_iters must be >= 1");
+  if (K < 1) return fail(c, SOR_EINVAL, "check_every must be >= 1");
+  return SOR_OK;
+}
+
+sor_status solve_plain_on(sor_ctx *c, int prec, const Layout &L, void *u, const void *bdy,
+                          const void *rhs, void *A, void *B, void *F, Ctl *ctl, double omega,
+                          const Sched &sc, hipStream_t s, sor_result *out, double *hist) {
+  const int n = L.n;
+  unsigned *bad = &ctl->input_nonfinite;
+  // The input flag must start clear: a reset moves it out of the way (the
+  // reset at the start of the sweeps then takes what packing finds).
+  HIP_TRY(c, launch_ctl_reset(ctl, s));
   HIP_TRY(c, launch_pack(prec, u, bdy, A, B, L.pitch, n, bad, s));
   if (rhs) HIP_TRY(c, launch_pack_rhs(prec, rhs, F, L.pitch, n, bad, s));
   *out = sor_result{};
   out->rel_residual = NAN;
-  const Sched sc{max_iters, K, tol};
   void *res_grid = A;
-  st = run_sweeps(c, prec, L, A, B, F, omega, sc, s, out, hist, &res_grid);
+  sor_status st = run_sweeps(c, prec, L, A, B, rhs ? F : nullptr, omega, sc, s, out, hist,
+                             &res_grid, 0, ctl);
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(prec, res_grid, u, L.pitch, n, s));
     HIP_TRY(c, hipStreamSynchronize(s));
@@ -444,11 +487,13 @@ sor_status solve_plain(sor_ctx *c, int prec, T *u, const T *bdy, const T *rhs,
   return st;
 }
 
-}  // namespace
+}  // namespace sor
 
 extern "C" {
 
-const char *sor_version(void) { return "sor 0.1.0 gfx950"; }
+const char *sor_version(void) { return "sor 0.2.0 gfx950"; }
+
+double sor_omega_opt(int32_t n) { return sor::omega_opt(n); }
 
 sor_status sor_ctx_create(int device, sor_ctx **out) {
   if (!out) return SOR_EINVAL;
@@ -469,7 +514,9 @@ sor_status sor_ctx_create(int device, sor_ctx **out) {
     sor_ctx_destroy(c);
     return SOR_ENOMEM;
   }
-  if (ensure(c, kCtlBuf, sizeof(Ctl)) != SOR_OK) {
+  // Two control blocks: the solve's, and one for a truncated re-run that
+  // must report non-finite values (see run_sweeps).
+  if (ensure(c, kCtlBuf, 2 * sizeof(Ctl)) != SOR_OK) {
     sor_ctx_destroy(c);
     return SOR_ENOMEM;
   }
@@ -658,7 +705,7 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
     res_grid = (out->passes & 1) ? B : A;
   } else {
     st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid,
-                    pass_ordering(ordering));
+                    pass_ordering(ordering), ctl);
   }
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));
@@ -825,7 +872,8 @@ sor_status sor_solve_mixed(sor_ctx *c, double *u, const double *bdy, const doubl
     const Sched sc{inner_iters, inner_iters, 0.0};
     void *res_grid = EA;
     sor_result ir{};
-    st = run_sweeps(c, plo, Llo, EA, EB, R, omega, sc, s, &ir, nullptr, &res_grid);
+    st = run_sweeps(c, plo, Llo, EA, EB, R, omega, sc, s, &ir, nullptr, &res_grid, 0,
+                    (Ctl *)c->bufs[kCtlBuf].p);
     if (st == SOR_ENONFINITE) { result = st; break; }
     if (st != SOR_NOT_CONVERGED && st != SOR_OK) return st;
     inner_total += inner_iters;

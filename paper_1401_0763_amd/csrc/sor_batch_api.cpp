@@ -444,7 +444,7 @@ sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *b
   }
   std::vector<double> hb(4 * (size_t)n, 1.0);
   hipError_t he = hipMemcpy(bdy, hb.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
-  const double omega = 2.0 / (1.0 + std::sin(M_PI / (n + 1)));
+  const double omega = omega_opt(n);
   const int iters = 96;                                 // divisible by 1, 2, 4
   std::vector<sor_grid_desc> gd((size_t)G);
   std::vector<sor_mixed_desc> md((size_t)G);

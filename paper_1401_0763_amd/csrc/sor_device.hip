@@ -81,6 +81,7 @@ __global__ void ctl_reset_kernel(Ctl *ctl) {
     ctl->nonfinite = ctl->input_nonfinite;   // inputs packed for this solve
     ctl->input_nonfinite = 0;
     ctl->stop = 0;
+    ctl->stop_tentative = 0;
     ctl->it_base = 0;
     ctl->stop_iter = 0;
     ctl->stop_max = 0.0;

@@ -62,6 +62,8 @@ bool is_device_ptr(sor_ctx *c, const void *p);
 sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
                         const void *rhs, int32_t n, double omega);
 int prec_index(int bits);
+// Young's optimal omega 2/(1 + sin(pi/(n+1))) (sor_omega_opt).
+double omega_opt(int n);
 void batch_state_free(sor_ctx *c);
 void mix_state_free(sor_ctx *c);
 // Segment rows chosen from the grid side for one plain solve: as many tiles
@@ -83,6 +85,18 @@ sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois);
 // above when none was set.
 sor_tiling batch_tiling(sor_ctx *c, int prec, int n);
 void clear_tuning(sor_ctx *c, int prec);
+sor_status check_sched(sor_ctx *c, double tol, int64_t max_iters, int64_t K);
+// One plain red-black solve (prec kF64 or kF32) on caller-provided working
+// grids of layout L (origins A, B and, with a source, F) and two control
+// blocks (ctl, ctl + 1): pack, sweep passes with device-side checks, unpack.
+// Arguments must already be validated.  Allocates nothing while the
+// context's profiling is off.
+sor_status solve_plain_on(sor_ctx *c, int prec, const Layout &L, void *u, const void *bdy,
+                          const void *rhs, void *A, void *B, void *F, Ctl *ctl, double omega,
+                          const Sched &sc, hipStream_t s, sor_result *out, double *hist);
+// Per-device set-up of the allocation-free entry point (sor_noalloc.hip),
+// called by sor_ctx_create with the device current.
+sor_status noalloc_init(sor_ctx *c);
 
 }  // namespace sor
 

@@ -52,6 +52,9 @@ struct alignas(256) Ctl {
   unsigned int nonfinite;   // sticky: a value became NaN or infinite
   int stop;                 // 0 running, 1 converged, 2 non-finite
   unsigned int input_nonfinite;  // set by packing when an input is not finite
+  int stop_tentative;       // 1: converged inside a pass that also made a
+                            // non-finite value (the truncated re-run decides)
+  int pad_;
   long long it_base;        // iterations completed by finished passes
   long long stop_iter;      // iteration whose check passed
   double stop_max;

@@ -159,9 +159,16 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
       }
     }
     if (nonf) {
-      stop = 2;
-      ctl->stop_iter = it0 + t_run;
-      ctl->stop_max = it_max[t_run - 1];
+      if (stop == 1 && ctl->stop_iter < it0 + t_run) {
+        // The rule was met at an iteration inside the pass, and some cell is
+        // non-finite by the pass's end: whether it already was at the
+        // stopping iteration is decided by the truncated re-run.
+        ctl->stop_tentative = 1;
+      } else {
+        stop = 2;
+        ctl->stop_iter = it0 + t_run;
+        ctl->stop_max = it_max[t_run - 1];
+      }
     }
     ctl->it_base = it0 + t_run;
     ctl->passes_done += 1;
@@ -275,9 +282,13 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // out-of-range offset.
 //
 // m[t] receives the largest |u' - u| of iteration t over the tile's core
-// cells (0 in halo lanes).  A non-finite value first appears, from finite
-// operands, as an infinity whose change is infinite, so bad is set when some
-// maximum is not finite (non-finite inputs are caught when they are packed).
+// cells (0 in halo lanes).  bad is set when an interior core cell is not
+// finite at the end of the pass, or some maximum is not finite.  Non-finite
+// values are absorbing for interior cells (an infinite cell's next update is
+// inf - inf or NaN, and a NaN stays NaN), so a cell that turns non-finite at
+// any iteration of the pass is non-finite when its row is stored; the maxima
+// alone would miss a NaN made from finite operands (+inf + -inf), because
+// the max drops NaN.  Non-finite inputs are caught when they are packed.
 // ---------------------------------------------------------------------------
 template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
@@ -325,6 +336,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   const unsigned st_off = lane_store ? lane_off : kDrop;
   const int from_lo = ((lane + 63) & 63) << 2;   // permute address: lane - 1
   const int from_hi = ((lane + 1) & 63) << 2;    // permute address: lane + 1
+  bool fin = true;                               // every stored interior cell finite
 
   ct w[W][V];                                    // row window
   ct fw[POIS ? W : 1][V];                        // h*h*f of the window rows
@@ -541,8 +553,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       for (int v = 0; v < V; ++v) x.v[v] = (st)w[so][v];
       buf_store<P, COH>(x, rout, st_off | (row_ok ? 0u : kDrop),
                    row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
+      // Interior columns are those with a nonzero relaxation factor.
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        fin = fin && (!row_ok || omc[v] == (ct)0 || __builtin_isfinite(w[so][v]));
     });
   }
+  bad = bad | (lane_store && !fin);
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     if (!lane_core) m[t] = (ct)0;

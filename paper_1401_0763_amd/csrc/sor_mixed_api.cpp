@@ -661,7 +661,7 @@ sor_status sor_server_submit(sor_server *srv, const sor_request *req, uint64_t *
   if (n < 1 || n > 4096) return SOR_EINVAL;
   if (!(req->rel_tol >= 0.0) || !(req->corr_tol >= 0.0) || req->max_outer < 0) return SOR_EINVAL;
   double omega = req->omega;
-  if (!(omega > 0.0)) omega = 2.0 / (1.0 + std::sin(M_PI / (n + 1)));
+  if (!(omega > 0.0)) omega = omega_opt(n);
   if (!(omega < 2.0)) return SOR_EINVAL;
   Request *q = new (std::nothrow) Request;
   if (!q) return SOR_ENOMEM;

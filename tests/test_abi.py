@@ -79,3 +79,19 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         sor.load_library()
     with pytest.raises(ImportError):
         sor.version()
+
+
+def test_omega_opt_host_function():
+    """sor_omega_opt is a host function (no device access): Young's optimum
+    2 / (1 + sin(pi/(n+1))) as the library uses it where no omega is given."""
+    import ctypes
+    import math
+    lib = ctypes.CDLL(LIB)
+    lib.sor_omega_opt.restype = ctypes.c_double
+    lib.sor_omega_opt.argtypes = [ctypes.c_int32]
+    for n in (1, 2, 16, 32, 256, 4096, 65536):
+        assert lib.sor_omega_opt(n) == 2.0 / (1.0 + math.sin(math.pi / (n + 1)))
+    assert math.isnan(lib.sor_omega_opt(0))
+    # the closed form of the survey's table (n = 256 and 4096)
+    assert abs(lib.sor_omega_opt(256) - 1.975847650301681) < 1e-15
+    assert abs(lib.sor_omega_opt(4096) - 1.998467568850995) < 1e-15
