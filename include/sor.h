@@ -172,6 +172,30 @@ sor_status sor_solve_f64(sor_ctx *ctx, double *u, const double *boundary,
                          sor_result *out, double *max_hist);
 
 /*
+ * sor_solve_f64 for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, layout, ownership, method, results and errors, bit for
+ * bit the same u, result and max_hist, but the working grids and control
+ * blocks live in a fixed 64 MiB region of device memory that the library
+ * holds on each GPU it runs on until the process ends, so the call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine).
+ *   Limit: the working memory of side n must fit the region, which holds
+ *   n <= 1951 without a source (rhs NULL) and n <= 1583 with one; larger n
+ *   returns SOR_EINVAL before any device work.
+ *   Sharing: every call of one process on one GPU uses the same region, so
+ *   calls that overlap in time on one GPU (other streams, threads or contexts)
+ *   race; serialise them.  Each call initialises what it reads.
+ *   The context's kernel and tiling settings apply; its profiling does not
+ *   (no events are recorded by this call).
+ * SOR_EDEVICE if the region's address could not be obtained when the context
+ * was created.
+ */
+sor_status sor_solve_f64_noalloc(sor_ctx *ctx, double *u, const double *boundary,
+                                 const double *rhs, int32_t n, double omega, double tol,
+                                 int64_t max_iters, int64_t check_every, void *stream,
+                                 sor_result *out, double *max_hist);
+
+/*
  * The same method with float storage and float arithmetic: omega is rounded
  * once to float, the source enters as fl32(h*h*f) with the product formed in
  * double, and changes are compared with tol in double.  Arguments as for

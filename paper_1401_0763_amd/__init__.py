@@ -121,7 +121,8 @@ def _declare(lib):
     lib.sor_ctx_tiling_for.restype = ctypes.c_int
     solve_args = [P, P, P, P, i32, dbl, dbl, i64, i64, P,
                   ctypes.POINTER(_Result), P]
-    for name in ("sor_solve_f64", "sor_solve_f32", "sor_solve3d_f64"):
+    for name in ("sor_solve_f64", "sor_solve_f32", "sor_solve3d_f64",
+                 "sor_solve_f64_noalloc"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = ctypes.c_int
     lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
@@ -409,6 +410,20 @@ def solve_f64(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
         omega = omega_opt(n)
     ctx = ctx or context(u.device.index)
     return _solve_plain(ctx.lib.sor_solve_f64, torch.float64, u, boundary, rhs,
+                        omega, tol, max_iters, check_every, hist, ctx)
+
+
+def solve_f64_noalloc(u, boundary, rhs=None, omega=None, tol=1e-8, max_iters=100000,
+                      check_every=1, hist=False, ctx: Context | None = None) -> Result:
+    """solve_f64 through sor_solve_f64_noalloc: the library allocates no
+    device memory for the call (working grids in its fixed per-GPU region;
+    n <= 1951 Laplace, n <= 1583 with a source)."""
+    import torch
+    n = u.shape[0]
+    if omega is None:
+        omega = omega_opt(n)
+    ctx = ctx or context(u.device.index)
+    return _solve_plain(ctx.lib.sor_solve_f64_noalloc, torch.float64, u, boundary, rhs,
                         omega, tol, max_iters, check_every, hist, ctx)
 
 

@@ -508,6 +508,12 @@ sor_status sor_ctx_create(int device, sor_ctx **out) {
   sor_ctx *c = new (std::nothrow) sor_ctx;
   if (!c) return SOR_ENOMEM;
   c->device = device;
+  try {
+    c->err.reserve(512);        // error messages then fit without reallocation
+  } catch (...) {
+    delete c;
+    return SOR_ENOMEM;
+  }
   if (hipHostMalloc((void **)&c->host_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void **)&c->host_stats, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -520,6 +526,9 @@ sor_status sor_ctx_create(int device, sor_ctx **out) {
     sor_ctx_destroy(c);
     return SOR_ENOMEM;
   }
+  // Device address of the allocation-free solve's working memory on this
+  // device (resolved once per device; a failure is reported by that solve).
+  (void)noalloc_init(c);
   *out = c;
   return SOR_OK;
 }

@@ -52,6 +52,7 @@ struct sor_ctx {
   int occ_var[3][sor::kTMax + 1][2] = {};              // their pass blocks per CU (lazy)
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
   int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)
+  void *scratch = nullptr;                             // allocation-free solve's memory
 };
 
 namespace sor {
