@@ -10,6 +10,7 @@
 
 #include "sor_internal.h"
 
+#include <limits>
 #include <type_traits>
 
 // Rows a wavefront loads ahead of the row it is updating.
@@ -75,6 +76,9 @@ __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ float vfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double vfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+// High 32 bits of a double's bit pattern, all 32 of a float's.
+__device__ __forceinline__ unsigned high_bits(double x) { return (unsigned)__double2hiint(x); }
+__device__ __forceinline__ unsigned high_bits(float x) { return __float_as_uint(x); }
 
 // Spread consecutive tiles over the 8 XCDs in contiguous runs: workgroups are
 // dispatched round-robin over XCDs, so block b runs on XCD b % 8; mapping it
@@ -336,7 +340,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   const unsigned st_off = lane_store ? lane_off : kDrop;
   const int from_lo = ((lane + 63) & 63) << 2;   // permute address: lane - 1
   const int from_hi = ((lane + 1) & 63) << 2;    // permute address: lane + 1
-  bool fin = true;                               // every stored interior cell finite
+  // Non-finite test of the stored interior cells: the largest high word (sign
+  // cleared) of their bit patterns is at least that of infinity exactly when
+  // one of them is an infinity or a NaN; integer operations, two per cell.
+  unsigned fmask[V];                             // 0x7fffffff on interior cells
+#pragma unroll
+  for (int v = 0; v < V; ++v) fmask[v] = (lane_store && omc[v] != (ct)0) ? 0x7fffffffu : 0u;
+  unsigned fhi = 0;
 
   ct w[W][V];                                    // row window
   ct fw[POIS ? W : 1][V];                        // h*h*f of the window rows
@@ -553,13 +563,12 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       for (int v = 0; v < V; ++v) x.v[v] = (st)w[so][v];
       buf_store<P, COH>(x, rout, st_off | (row_ok ? 0u : kDrop),
                    row_ok ? (unsigned)(qo - a) * rowbytes : 0u);
-      // Interior columns are those with a nonzero relaxation factor.
+      const unsigned rmask = row_ok ? 0xffffffffu : 0u;
 #pragma unroll
-      for (int v = 0; v < V; ++v)
-        fin = fin && (!row_ok || omc[v] == (ct)0 || __builtin_isfinite(w[so][v]));
+      for (int v = 0; v < V; ++v) fhi = max(fhi, high_bits(w[so][v]) & fmask[v] & rmask);
     });
   }
-  bad = bad | (lane_store && !fin);
+  bad = bad | (fhi >= high_bits(std::numeric_limits<ct>::infinity()));
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     if (!lane_core) m[t] = (ct)0;
