@@ -37,9 +37,11 @@ Under "forms" the same line reports:
            and iterations to 1e-8 on 128^2 beside red-black;
 and, each against plain one-grid-at-a-time FP64 on the same GPU:
   mixed    4096^2 Poisson (f = N(0,1) + 2 pi^2 sin sin, seed 3): FP64 defect
-           correction around FP32 and binary16 inner sweeps vs plain FP64 SOR
-           to the same relative residual, errors against the exact discrete
-           solution (DST-I);
+           correction around FP32 inner sweeps vs plain FP64 SOR, each run to
+           its accuracy floor: relative residual, normwise backward error,
+           error against the exact discrete solution (DST-I) and difference
+           from the FP64 SOR result; binary16 inner storage at 1024^2 (the
+           largest side it accepts) beside FP32 there;
   batched  512 grids, sides log-uniform in [64, 1024] (seed 4), f = N(0,1) on
            odd grids, omega_opt, tol 1e-8: one persistent launch, FP64 (with
            the size rule's tiles and with autotuned tiles) and
@@ -160,11 +162,7 @@ def dst_exact(n, bdy, f):
     import numpy as np
     import scipy.fft
     h = 1.0 / (n + 1)
-    b = h * h * np.asarray(f, dtype=np.float64).copy()
-    b[0, :] += bdy[0:n]
-    b[-1, :] += bdy[n:2 * n]
-    b[:, 0] += bdy[2 * n:3 * n]
-    b[:, -1] += bdy[3 * n:4 * n]
+    b = rhs_b(n, bdy, f)
     s2 = np.sin(np.arange(1, n + 1) * np.pi * h / 2.0) ** 2
     lam = 4.0 * (s2[:, None] + s2[None, :])
     return scipy.fft.idstn(scipy.fft.dstn(b, type=1, norm="ortho") / lam, type=1,
@@ -197,49 +195,117 @@ def time_to(trace, target):
     return None
 
 
+def rhs_b(n, bdy, f):
+    """b = h*h*f + (boundary neighbours) of the h*h-scaled 5-point system."""
+    import numpy as np
+    h = 1.0 / (n + 1)
+    b = h * h * np.asarray(f, dtype=np.float64).copy()
+    b[0, :] += bdy[0:n]
+    b[-1, :] += bdy[n:2 * n]
+    b[:, 0] += bdy[2 * n:3 * n]
+    b[:, -1] += bdy[3 * n:4 * n]
+    return b
+
+
+def accuracy(sor, ctx, u, b_dev, f_dev, b_inf, exact, scale, ref=None):
+    """Relative residual ||r||_2/||b||_2, normwise backward error
+    ||r||_inf / (||A||_inf ||u||_inf + ||b||_inf) with ||A||_inf = 8 for the
+    h*h-scaled operator, error against the exact discrete solution and, with
+    ref, the largest difference from the FP64 SOR result, both relative to
+    the largest value."""
+    import numpy as np
+    sr, sb, rinf = sor.residual_f64(u, b_dev, f_dev, ctx=ctx)
+    uh = u.cpu().numpy()
+    out = {"rel_residual": math.sqrt(sr) / math.sqrt(sb),
+           "backward_error_inf": rinf / (8.0 * float(np.max(np.abs(uh))) + b_inf),
+           "max_err_vs_exact_rel": float(np.max(np.abs(uh - exact))) / scale}
+    if ref is not None:
+        out["max_rel_diff_vs_fp64"] = float(np.max(np.abs(uh - ref))) / float(np.max(np.abs(ref)))
+    return out
+
+
+def mixed_run(sor, ctx, torch, g, b, f, bits, max_outer, b_inf, exact, scale, ref, targets):
+    """One timed mixed-precision solve of max_outer corrections (default inner
+    count), then the same corrections one call at a time (identical
+    arithmetic: every correction starts from the residual of the current
+    iterate) for the backward error after each."""
+    n = g.n
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = sor.solve_mixed(u, b, f, g.omega, 0.0, max_outer, bits, 0, hist=True, ctx=ctx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    final = accuracy(sor, ctx, u, b, f, b_inf, exact, scale, ref)
+    steps = max(r.outer_steps, 1)
+    trace = [(dt * k / steps, k, float(x)) for k, x in enumerate(r.hist)]
+    u.zero_()
+    bw = []
+    for _ in range(r.outer_steps):
+        sor.solve_mixed(u, b, f, g.omega, 0.0, 1, bits, 0, ctx=ctx)
+        _, _, rinf = sor.residual_f64(u, b, f, ctx=ctx)
+        bw.append(rinf / (8.0 * float(u.abs().max()) + b_inf))
+    k_bw = next((k + 1 for k, x in enumerate(bw) if x <= 1e-10), None)
+    out = {"secs": round(dt, 3), "outer_steps": r.outer_steps,
+           "inner_iters_per_step": (max(n // 2, 1) + 3) // 4 * 4,
+           "rel_history": [float(x) for x in r.hist],
+           "backward_error_history": [float(f"{x:.3e}") for x in bw],
+           "best_rel_residual": float(min(r.hist)),
+           "secs_to": {str(t): time_to(trace, t) for t in targets},
+           "secs_to_backward_error_1e-10": None if k_bw is None else
+           round(dt * k_bw / steps, 3)}
+    out.update(final)
+    return out
+
+
 def form_mixed(sor, ctx, torch):
+    """The mixed-precision workload: FP64 defect correction around FP32 inner
+    sweeps at 4096^2 against plain FP64 SOR, both run to their accuracy
+    floors; binary16 inner storage at 1024^2, the largest side it accepts,
+    beside FP32 at that side."""
     import numpy as np
     from workloads import poisson_manufactured
-    n = 4096
-    g = poisson_manufactured(n, seed=3)
-    b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
-    f = torch.tensor(g.f, dtype=torch.float64, device="cuda")
-    exact = dst_exact(n, g.bdy, g.f)
-    scale = float(np.max(np.abs(exact)))
     targets = (1e-6, 1e-8, 1e-10)
-    out = {"workload": "poisson_manufactured_4096 (seed 3), omega_opt",
-           "note": "times to reach each relative residual; refinement step k is "
-                   "timed as k/steps of the whole run (every step does the same work)"}
-    # n/2 inner iterations per correction: each correction then reduces the
-    # residual about 20-fold, and n/2 beats n and 2n on time to 1e-8.
-    inner = n // 2
-    for bits, max_outer in ((32, 14), (16, 6)):
-        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
+    out = {"workload": "poisson_manufactured_4096 (seed 3), omega_opt; binary16 at "
+                       "poisson_manufactured_1024 (seed 3)",
+           "note": "refinement step k is timed as k/steps of the whole run (every step "
+                   "does the same work); backward error = ||r||_inf / (8 ||u||_inf + "
+                   "||b||_inf) in the h*h-scaled system; inner iterations per correction: "
+                   "the default, n/2 rounded up to a multiple of 4"}
+    for n in (4096, 1024):
+        g = poisson_manufactured(n, seed=3)
+        b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
+        f = torch.tensor(g.f, dtype=torch.float64, device="cuda")
+        exact = dst_exact(n, g.bdy, g.f)
+        scale = float(np.max(np.abs(exact)))
+        b_inf = float(np.max(np.abs(rhs_b(n, g.bdy, g.f))))
+        # Plain FP64 SOR to its floor: chunks of 2000 iterations until the
+        # relative residual stops falling (three chunks without a new best).
+        u64 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        trace, best, stale = [], float("inf"), 0
         t0 = time.perf_counter()
-        r = sor.solve_mixed(u, b, f, g.omega, 0.0, max_outer, bits, inner, hist=True, ctx=ctx)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        steps = max(r.outer_steps, 1)
-        trace = [(dt * k / steps, k, float(x)) for k, x in enumerate(r.hist)]
-        err = float(np.max(np.abs(u.cpu().numpy() - exact))) / scale
-        out[f"fp{bits}_refine"] = {
-            "secs": round(dt, 3), "outer_steps": r.outer_steps,
-            "inner_iters_per_step": inner,
-            "rel_history": [float(x) for x in r.hist],
-            "best_rel_residual": float(min(r.hist)),
-            "secs_to": {str(t): time_to(trace, t) for t in targets},
-            "max_err_vs_exact_rel": err}
-    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
-    trace = []
-    torch.cuda.synchronize()
-    fp64_to_residual(sor, ctx, u, b, f, g.omega, 1e-10, 2000, 40000, trace)
-    torch.cuda.synchronize()
-    err = float(np.max(np.abs(u.cpu().numpy() - exact))) / scale
-    out["fp64_plain"] = {"secs": round(trace[-1][0], 3), "iterations": trace[-1][1],
-                         "best_rel_residual": min(r for _, _, r in trace),
-                         "secs_to": {str(t): time_to(trace, t) for t in targets},
-                         "max_err_vs_exact_rel": err}
+        while stale < 3 and len(trace) < 40:
+            sor.solve_f64(u64, b, f, g.omega, 0.0, 2000, 2000, ctx=ctx)
+            sr, sb, _ = sor.residual_f64(u64, b, f, ctx=ctx)
+            rel = math.sqrt(sr) / math.sqrt(sb)
+            trace.append((time.perf_counter() - t0, 2000 * (len(trace) + 1), rel))
+            stale = 0 if rel < 0.99 * best else stale + 1
+            best = min(best, rel)
+        ref = u64.cpu().numpy()
+        key = "" if n == 4096 else f"_{n}"
+        rec = {"iterations": trace[-1][1], "secs": round(trace[-1][0], 3),
+               "best_rel_residual": best,
+               "secs_to": {str(t): time_to(trace, t) for t in targets}}
+        rec.update(accuracy(sor, ctx, u64, b, f, b_inf, exact, scale))
+        out[f"fp64_plain{key}"] = rec
+        out[f"fp32_refine{key}"] = mixed_run(sor, ctx, torch, g, b, f, 32, 14 if n == 4096 else 12,
+                                             b_inf, exact, scale, ref, targets)
+        if n == 1024:
+            out["fp16_refine_1024"] = mixed_run(sor, ctx, torch, g, b, f, 16, 30, b_inf, exact,
+                                                scale, ref, targets)
+        del u64, b, f
+    out["fp16_refine"] = ("not run at 4096^2: binary16 inner storage is accepted for n <= "
+                          "1024 only (it stalls near relative residual 1e2-1e3 from n = 1536)")
     return out
 
 

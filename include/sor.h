@@ -336,7 +336,23 @@ sor_status sor_residual_f64(sor_ctx *ctx, const double *u,
  *   bounds the infinity norm of the inverse of the unscaled 5-point operator
  *   on the unit square, keeping the scaled correction below about 2^14);
  *   the correction is added as u + (double)e * 2^-p.
- *   inner_iters <= 0 selects 2*n.  rel_hist: optional HOST array of
+ *   inner_iters <= 0 selects n/2 rounded up to a multiple of 4 (at least 4):
+ *   on Poisson problems from 256^2 to 4096^2 about n/2 reaches a relative
+ *   residual of 1e-8 in the least time of n/8 .. 2n (each correction lowers
+ *   rel about 20-fold); multiples of 4 let batched and served solves run
+ *   their faster fixed-depth kernel.
+ *   binary16 storage is accepted for n <= 1024 only (SOR_EINVAL above; the
+ *   same limit holds for the batched solve and the request server).  Its
+ *   11-bit significand cannot hold a smooth correction: once a cell's change
+ *   per inner iteration is below half an ulp of its value the sweeps stop
+ *   moving it, and the rounding of a smooth field is itself smooth, so the
+ *   correction is wrong in the components SOR is slowest to remove.
+ *   Measured: the refinement reaches rel 1e-8 within 30 corrections up to
+ *   n = 1024; from n = 1536 it stalls near rel 1e2..1e3 whatever the inner
+ *   count.  The loop does not stop when rel grows: the first corrections
+ *   from a zero correction at omega near 2 raise rel (up to about n/10-fold)
+ *   on problems that then converge.
+ *   rel_hist: optional HOST array of
  *   max_outer + 1 doubles receiving rel before each correction and at exit.
  *   With ||b||_2 = 0, rel is ||r||_2.  The norms are plain FP64 sums of
  *   squares, so entries of r or b above about 1e150 overflow them.
@@ -389,6 +405,15 @@ sor_status sor_batch_solve_f64(sor_ctx *ctx, const sor_grid_desc *grids,
                                int32_t count, void *stream, sor_result *results);
 
 /*
+ * Retire times of the grids of the context's most recent sor_batch_solve_f64
+ * (measurement; not in the paper): done_ms[g] (HOST, count doubles) receives
+ * the device wall-clock milliseconds from the start of the persistent launch
+ * to the moment grid g's stopping rule retired it (NaN for a grid that did not
+ * retire).  SOR_EINVAL unless count equals that solve's grid count.
+ */
+sor_status sor_batch_last_times(const sor_ctx *ctx, int32_t count, double *done_ms);
+
+/*
  * Tiling autotuner for plain solves: times blocked passes of every candidate
  * tiling (1..8 iterations per pass x 16..768 rows per tile) on a scratch
  * n x n Laplace grid of the given storage precision (64 or 32 bits) with HIP
@@ -429,7 +454,7 @@ typedef struct sor_mixed_desc {
                                  |e| is below corr_tol                      */
     int64_t max_outer;        /* >= 0 corrections                           */
     int64_t inner_iters;      /* > 0 inner iterations per correction
-                                 (<= 0 selects 2n)                          */
+                                 (<= 0: n/2 rounded up to a multiple of 4)  */
 } sor_mixed_desc;
 
 /*
@@ -470,7 +495,7 @@ typedef struct sor_request {
     double rel_tol;
     double corr_tol;
     int64_t max_outer;
-    int64_t inner_iters;      /* <= 0 selects 2n                            */
+    int64_t inner_iters;      /* <= 0: n/2 rounded up to a multiple of 4    */
 } sor_request;
 
 typedef struct sor_request_info {
@@ -483,7 +508,9 @@ typedef struct sor_request_info {
 sor_status sor_server_create(int device, int32_t inner_bits, size_t hbm_budget,
                              int32_t max_slots, double slice_ms, sor_server **out);
 /* Copy a request in and queue it; *ticket identifies it.  SOR_EBUSY if the
- * request alone exceeds the memory budget (it could never be admitted). */
+ * request alone exceeds the memory budget (it could never be admitted);
+ * SOR_EINVAL for n outside 1..4096 (1..1024 on a binary16 server) or an
+ * invalid parameter. */
 sor_status sor_server_submit(sor_server *srv, const sor_request *req, uint64_t *ticket);
 /* If the request has finished, fill *info and u_out (HOST n*n, may be NULL),
  * release it and return its status (SOR_OK, SOR_NOT_CONVERGED, SOR_ENONFINITE);

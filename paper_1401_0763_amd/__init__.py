@@ -125,6 +125,8 @@ def _declare(lib):
                  "sor_solve_f64_noalloc"):
         getattr(lib, name).argtypes = solve_args
         getattr(lib, name).restype = ctypes.c_int
+    lib.sor_batch_last_times.argtypes = [P, i32, P]
+    lib.sor_batch_last_times.restype = ctypes.c_int
     lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
     lib.sor_solve_variant_f64.restype = ctypes.c_int
     lib.sor_ctx_set_variant_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
@@ -265,6 +267,13 @@ class Context:
         t = _Tiling()
         self._check(self.lib.sor_autotune(self.handle, int(bits), int(n), ctypes.byref(t)))
         return t.iters_per_pass, t.seg_rows
+
+    def batch_times(self, count: int) -> list[float]:
+        """Retire time (ms after the persistent launch began) of each grid of
+        the most recent batch_solve_f64 on this context."""
+        out = (ctypes.c_double * int(count))()
+        self._check(self.lib.sor_batch_last_times(self.handle, int(count), out), (OK,))
+        return list(out)
 
     def autotune_batch(self, bits: int, n: int) -> tuple[int, int]:
         """Time candidate tilings on a scratch batch of n x n grids; returns

@@ -826,7 +826,9 @@ sor_status sor_solve_mixed(sor_ctx *c, double *u, const double *bdy, const doubl
   if (!(rel_tol >= 0.0)) return fail(c, SOR_EINVAL, "rel_tol must be >= 0");
   if (max_outer < 0) return fail(c, SOR_EINVAL, "max_outer must be >= 0");
   if (inner_bits != 32 && inner_bits != 16) return fail(c, SOR_EINVAL, "inner_bits must be 32 or 16");
-  if (inner_iters <= 0) inner_iters = 2 * (int64_t)n;
+  if (inner_bits == 16 && n > kMaxN16)
+    return fail(c, SOR_EINVAL, "binary16 inner storage supports n <= %d (n = %d)", kMaxN16, n);
+  if (inner_iters <= 0) inner_iters = mixed_inner_default(n);
   hipStream_t s = (hipStream_t)stream;
   const int plo = inner_bits == 32 ? kF32 : kF16;
   const Layout L = make_layout(n, kF64);

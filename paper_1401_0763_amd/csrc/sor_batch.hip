@@ -10,27 +10,35 @@
 
 namespace sor {
 
-// Depths a batched pass may have; a re-run or a final partial pass is split
-// greedily into these.
+// Depth of the next batched pass: the grid's depth, or what is left of a
+// re-run or of the iteration limit.
 __device__ __forceinline__ int batch_depth(long long left, int T) {
-  if (T >= 4 && left >= 4) return 4;
-  if (T >= 2 && left >= 2) return 2;
-  return 1;
+  return left < T ? (int)left : T;
 }
 
 // Grid g finished the pass whose tiles were queued: evaluate Algorithm 1's
 // check for its iterations, then queue the next pass or retire the grid.
-// Called by the whole wave that completed the pass's last tile.
-template <int P>
-__device__ void batch_grid_finish(BGrid *G, int g, BQueue *q, BItem *ring) {
+// Called by the whole wave that completed the pass's last tile.  Not inlined:
+// merged into the kernel's loop it raises the kernel's register count enough
+// to halve the resident wavefronts.
+//
+// The main kernel (TAIL false) runs only full passes of depth TM.  A grid
+// whose next pass is shorter (a re-run up to an iteration inside the last
+// pass, or the last iterations before max_iters) is parked: its pass goes to
+// the tail queue (tq, tring), whose kernel runs after the main one and
+// applies passes of any depth.
+template <int P, int TM, bool TAIL>
+__device__ __noinline__ void batch_grid_finish(BGrid *G, int g, BQueue *q, BItem *ring,
+                                               BQueue *tq, BItem *tring) {
   const int lane = threadIdx.x & 63;
   const int T = G->pass_T;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double it_max[kTMax];
 #pragma unroll
   for (int t = 0; t < kTMax; ++t) {
     unsigned long long b = 0;
     if (lane < kBSlots && t < T) {
-      b = __hip_atomic_load(&G->slots[lane][t], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+      b = __hip_atomic_load(&G->slots[lane][t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&G->slots[lane][t], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     it_max[t] = wave_max(__longlong_as_double((long long)b));
@@ -96,24 +104,35 @@ __device__ void batch_grid_finish(BGrid *G, int g, BQueue *q, BItem *ring) {
       }
     }
     if (next_T) {
-      nt = blocked_ntiles(P, G->n, next_T, G->seg_rows);
+      nt = blocked_ntiles(P, G->n, TM, G->seg_rows);
       G->pass_T = next_T;
       G->ntiles = nt;
+    } else {
+      G->t_done = wall_clock64();
     }
     __hip_atomic_store(&G->tiles_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   next_T = __shfl(next_T, 0, 64);
   nt = __shfl(nt, 0, 64);
-  if (next_T) {
+  const bool park = !TAIL && next_T != 0 && next_T < TM;
+  if (park) {
+    if (lane == 0) {
+      __hip_atomic_fetch_add(&tq->remaining, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&q->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    bq_publish(tq, tring, g, nt);
+  } else if (next_T) {
     bq_publish(q, ring, g, nt);
   } else if (lane == 0) {
     __hip_atomic_fetch_add(&q->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-template <int P, int T, bool POIS>
-__device__ __forceinline__ void batch_tile(BGrid *G, int tile, double (&mx)[kTMax],
-                                           bool &bad) {
+// One tile of a pass of t_run (1..T) iterations (DYN; else exactly T), in
+// the tile geometry of depth T (every pass of a grid has the same tiles).
+template <int P, int T, bool POIS, bool DYN>
+__device__ __forceinline__ void batch_tile(BGrid *G, int tile, int t_run,
+                                           double (&mx)[kTMax], bool &bad) {
   using ct = typename PT<P>::ct;
   constexpr int V = PT<P>::V;
   constexpr int S = 2 * T;
@@ -131,36 +150,40 @@ __device__ __forceinline__ void batch_tile(BGrid *G, int tile, double (&mx)[kTMa
   v.omega = G->omega;
   ct m[T];
   // Tiles of this grid's next pass may run on other XCDs in this same launch.
-  blocked_tile<P, T, POIS, kCohAgent>(v, tile, m, bad);
+  blocked_tile<P, T, POIS, kCohAgent, 0, DYN>(v, tile, m, bad, 2 * t_run);
 #pragma unroll
   for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
 }
 
 // Persistent batched sweep: each wavefront takes items until no grid has work
 // left.  Items of a grid's pass run in any order on any wavefront; the last
-// one to finish closes the pass.
-template <int P>
-__global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BItem *ring) {
+// one to finish closes the pass.  The main kernel has one tile body, of the
+// fixed depth TM and with a source term (a grid without a source reads it as
+// zero), which keeps the register count of a single pass kernel: a second
+// body in the same kernel (another depth, or one without the source term),
+// or a depth chosen at run time, costs it half its resident wavefronts.  The
+// tail kernel (TAIL) applies the shorter passes of the parked grids with a
+// run-time depth.
+template <int P, int TM, bool POIS, bool TAIL>
+__global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BItem *ring,
+                                                   BQueue *tq, BItem *tring) {
   const int lane = threadIdx.x & 63;
+  if (lane == 0) {                          // launch start, for retire times
+    long long zero = 0;
+    __hip_atomic_compare_exchange_strong(&q->t0, &zero, (long long)wall_clock64(),
+                                         __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  }
   for (;;) {
     int g, tile;
     if (!bq_take(q, ring, g, tile)) return;
     BGrid *G = &grids[g];
-    const int T = G->pass_T;
-    const bool pois = G->F != nullptr;
+    const int T = TAIL ? G->pass_T : TM;
     double mx[kTMax];
 #pragma unroll
     for (int t = 0; t < kTMax; ++t) mx[t] = 0.0;
     bool bad = false;
-    if (pois) {
-      if (T == 4) batch_tile<P, 4, true>(G, tile, mx, bad);
-      else if (T == 2) batch_tile<P, 2, true>(G, tile, mx, bad);
-      else batch_tile<P, 1, true>(G, tile, mx, bad);
-    } else {
-      if (T == 4) batch_tile<P, 4, false>(G, tile, mx, bad);
-      else if (T == 2) batch_tile<P, 2, false>(G, tile, mx, bad);
-      else batch_tile<P, 1, false>(G, tile, mx, bad);
-    }
+    batch_tile<P, TM, POIS, TAIL>(G, tile, T, mx, bad);
     const bool anybad = __ballot(bad) != 0;
     unsigned prev = 0;
     if (lane == 0) {
@@ -176,7 +199,7 @@ __global__ __launch_bounds__(64) void batch_kernel(BGrid *grids, BQueue *q, BIte
       prev = count_item_done(&G->tiles_done);   // grid stores are device-scope
     }
     prev = __shfl(prev, 0, 64);
-    if (prev == (unsigned)G->ntiles - 1) batch_grid_finish<P>(G, g, q, ring);
+    if (prev == (unsigned)G->ntiles - 1) batch_grid_finish<P, TM, TAIL>(G, g, q, ring, tq, tring);
   }
 }
 
@@ -237,16 +260,27 @@ hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, int waves, hipStream_t s) {
-  hipLaunchKernelGGL(batch_kernel<kF64>, dim3(waves), dim3(64), 0, s, grids, q, ring);
+hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, BQueue *tq, BItem *tring,
+                            int waves, bool tail, hipStream_t s) {
+  if (tail)
+    hipLaunchKernelGGL((batch_kernel<kF64, kBatchT, true, true>), dim3(waves), dim3(64), 0, s,
+                       grids, q, ring, tq, tring);
+  else
+    hipLaunchKernelGGL((batch_kernel<kF64, kBatchT, true, false>), dim3(waves), dim3(64), 0, s,
+                       grids, q, ring, tq, tring);
   return hipGetLastError();
 }
 
-int batch_waves_per_cu_f64() {
+int batch_waves_per_cu_f64(bool tail) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, batch_kernel<kF64>, 64, 0) != hipSuccess) {
+  const hipError_t e =
+      tail ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &blocks, batch_kernel<kF64, kBatchT, true, true>, 64, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                 &blocks, batch_kernel<kF64, kBatchT, true, false>, 64, 0);
+  if (e != hipSuccess) {
     (void)hipGetLastError();
-    return 8;
+    return 4;
   }
   return blocks > 0 ? blocks : 1;
 }

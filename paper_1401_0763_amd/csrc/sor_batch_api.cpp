@@ -35,6 +35,8 @@ struct BatchState {
   long long wall_khz = 0;
   hipGraphExec_t exec = nullptr;
   std::vector<long long> sig;            // shapes the graph was recorded for
+  std::vector<double> done_ms;           // retire time of each grid of the last
+                                         // batched FP64 solve (ms after launch start)
   // size class -> tiling, per precision: autotuner results for plain solves
   // (sor_autotune) and for grids inside batched launches (sor_autotune_batch)
   std::map<int, sor_tiling> tune[3];
@@ -140,7 +142,7 @@ sor_status batch_state(sor_ctx *c, BatchState **out) {
     HIP_TRY(c, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIP_TRY(c, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     HIP_TRY(c, hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
-    HIP_TRY(c, hipHostMalloc((void **)&b->h_queue, sizeof(BQueue), hipHostMallocDefault));
+    HIP_TRY(c, hipHostMalloc((void **)&b->h_queue, 2 * sizeof(BQueue), hipHostMallocDefault));
     int khz = 0;
     HIP_TRY(c, hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device));
     b->wall_khz = khz > 0 ? khz : 100000;
@@ -159,14 +161,6 @@ sor_status host_grow(sor_ctx *c, T **p, size_t *cap, size_t need) {
   HIP_TRY(c, hipHostMalloc((void **)p, n * sizeof(T), hipHostMallocDefault));
   *cap = n;
   return SOR_OK;
-}
-
-// Batch depths are 1, 2 or 4 iterations per pass.
-int batch_T(int T) { return T >= 4 ? 4 : T >= 2 ? 2 : 1; }
-long long batch_depth_host(long long left, int T) {
-  if (T >= 4 && left >= 4) return 4;
-  if (T >= 2 && left >= 2) return 2;
-  return 1;
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -195,12 +189,15 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
   sor_status st = batch_state(c, &bs);
   if (st != SOR_OK) return st;
 
-  // Arena layout, tilings and work estimates.
+  // Arena layout, tilings and work estimates.  Every grid runs in one
+  // persistent kernel of fixed depth kBatchT (queue 0), followed by a tail
+  // kernel (queue 1) for the passes shorter than that depth.
   std::vector<Layout> lay(count);
   std::vector<size_t> offA(count), offB(count), offF(count);
-  std::vector<sor_tiling> til(count);
+  std::vector<int> seg(count);
   size_t arena = 0;
-  long long total_items = 0, max_items = 0;
+  long long items[2] = {0, 0}, max_items = 0;
+  int ngrids[2] = {0, 0};
   int max_n = 0;
   for (int g = 0; g < count; ++g) {
     const int n = grids[g].n;
@@ -209,31 +206,34 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
     offA[g] = arena; arena += bytes;
     offB[g] = arena; arena += bytes;
     if (grids[g].rhs) { offF[g] = arena; arena += bytes; }
-    til[g] = batch_tiling(c, kF64, n);
-    til[g].iters_per_pass = batch_T(til[g].iters_per_pass);
-    const int T0 = (int)batch_depth_host(grids[g].max_iters, til[g].iters_per_pass);
-    total_items += blocked_ntiles(kF64, n, T0, til[g].seg_rows);
-    long long most = 0;
-    for (int t : {1, 2, 4})
-      most = std::max<long long>(most, blocked_ntiles(kF64, n, t, til[g].seg_rows));
-    max_items += most;
+    seg[g] = batch_tiling(c, kF64, n).seg_rows;
+    const int nt = blocked_ntiles(kF64, n, kBatchT, seg[g]);
+    const int q = grids[g].max_iters < kBatchT ? 1 : 0;      // first pass short: tail
+    items[q] += nt;
+    ngrids[q] += 1;
+    max_items += nt;
     max_n = std::max(max_n, n);
   }
-  // Ring capacity: every grid has at most one pass queued, plus one slot per
-  // waiting wavefront; doubled and rounded to a power of two.
+  const long long total_items = items[0] + items[1];
+  // Ring capacity per queue: every grid has at most one pass queued, plus one
+  // slot per waiting wavefront; doubled and rounded to a power of two.
   int cus = 0;
   HIP_TRY(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-  const int waves = std::max(1, cus) * batch_waves_per_cu_f64();
-  unsigned long long cap = 1024;
-  while (cap < 2ull * (unsigned long long)(max_items + waves) + 1024) cap <<= 1;
+  int waves[2];
+  unsigned long long cap[2];
+  for (int q = 0; q < 2; ++q) {
+    waves[q] = std::max(1, cus) * batch_waves_per_cu_f64(q == 1);
+    cap[q] = 1024;
+    while (cap[q] < 2ull * (unsigned long long)(max_items + waves[q]) + 1024) cap[q] <<= 1;
+  }
 
   if ((st = ensure(c, kBatchArena, arena)) ||
       (st = ensure(c, kBatchGrids, sizeof(BGrid) * (size_t)count)) ||
-      (st = ensure(c, kBatchQueue, sizeof(BQueue))) ||
-      (st = ensure(c, kBatchRing, sizeof(BItem) * cap)))
+      (st = ensure(c, kBatchQueue, 2 * sizeof(BQueue))) ||
+      (st = ensure(c, kBatchRing, sizeof(BItem) * (cap[0] + cap[1]))))
     return st;
   if ((st = host_grow(c, &bs->h_grids, &bs->h_grids_cap, (size_t)count)) ||
-      (st = host_grow(c, &bs->h_items, &bs->h_items_cap, (size_t)total_items)))
+      (st = host_grow(c, &bs->h_items, &bs->h_items_cap, (size_t)std::max(1LL, total_items))))
     return st;
 
   char *base = (char *)c->bufs[kBatchArena].p;
@@ -250,48 +250,55 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
     G.user_f = d.rhs;
     G.pitch = lay[g].pitch;
     G.n = d.n;
-    G.T = til[g].iters_per_pass;
-    G.seg_rows = til[g].seg_rows;
+    G.T = kBatchT;
+    G.seg_rows = seg[g];
     G.omega = d.omega;
     G.tol = d.tol;
     G.max_iters = d.max_iters;
     G.check_every = d.check_every;
     G.pass_budget = LLONG_MAX;
-    G.pass_T = (int)batch_depth_host(d.max_iters, G.T);
-    G.ntiles = blocked_ntiles(kF64, d.n, G.pass_T, G.seg_rows);
+    G.pass_T = (int)std::min<long long>(d.max_iters, kBatchT);
+    G.ntiles = blocked_ntiles(kF64, d.n, kBatchT, G.seg_rows);
     G.last_max = NAN;
   }
-  // Initial queue: pass 0 of every grid, largest expected work first (work
+  // Initial queues: pass 0 of every grid, largest expected work first (work
   // grows like n^3 at the optimal omega) so the longest chains start first.
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int x, int y) { return grids[x].n > grids[y].n; });
   const unsigned long long gen = ++bs->gen & 0xffffffull;
-  unsigned long long idx = 0;
-  for (int g : order)
-    for (int t = 0; t < bs->h_grids[g].ntiles; ++t, ++idx) {
-      bs->h_items[idx].tag = bq_tag(gen, idx);
-      bs->h_items[idx].payload = ((unsigned long long)g << 32) | (unsigned)t;
+  unsigned long long idx[2] = {0, 0};
+  BItem *hit[2] = {bs->h_items, bs->h_items + items[0]};
+  for (int g : order) {
+    const BGrid &G = bs->h_grids[g];
+    const int q = G.pass_T < G.T ? 1 : 0;
+    for (int t = 0; t < G.ntiles; ++t, ++idx[q]) {
+      hit[q][idx[q]].tag = bq_tag(gen, idx[q]);
+      hit[q][idx[q]].payload = ((unsigned long long)g << 32) | (unsigned)t;
     }
-  BQueue &Q = *bs->h_queue;
-  std::memset(&Q, 0, sizeof(BQueue));
-  Q.head = 0;
-  Q.tail = idx;
-  Q.gen = gen;
-  Q.mask = cap - 1;
-  Q.remaining = count;
-  Q.error = 0;
-  Q.deadline_ticks = bs->wall_khz * 1000ll * 20;   // 20 s without progress
+  }
+  for (int q = 0; q < 2; ++q) {
+    BQueue &Q = bs->h_queue[q];
+    std::memset(&Q, 0, sizeof(BQueue));
+    Q.head = 0;
+    Q.tail = idx[q];
+    Q.gen = gen;
+    Q.mask = cap[q] - 1;
+    Q.remaining = ngrids[q];
+    Q.error = 0;
+    Q.deadline_ticks = bs->wall_khz * 1000ll * 20;   // 20 s without progress
+  }
 
   BGrid *dG = (BGrid *)c->bufs[kBatchGrids].p;
   BQueue *dQ = (BQueue *)c->bufs[kBatchQueue].p;
-  BItem *dR = (BItem *)c->bufs[kBatchRing].p;
+  BItem *dR[2] = {(BItem *)c->bufs[kBatchRing].p, (BItem *)c->bufs[kBatchRing].p + cap[0]};
   const std::vector<long long> sig = {
-      count, (long long)total_items, max_n, waves, (long long)cap,
-      (long long)(uintptr_t)base, (long long)(uintptr_t)dG, (long long)(uintptr_t)dQ,
-      (long long)(uintptr_t)dR, (long long)(uintptr_t)bs->h_grids,
-      (long long)(uintptr_t)bs->h_queue, (long long)(uintptr_t)bs->h_items};
+      count, items[0], items[1], max_n, waves[0], waves[1], (long long)cap[0],
+      (long long)cap[1], (long long)(uintptr_t)base, (long long)(uintptr_t)dG,
+      (long long)(uintptr_t)dQ, (long long)(uintptr_t)dR[0],
+      (long long)(uintptr_t)bs->h_grids, (long long)(uintptr_t)bs->h_queue,
+      (long long)(uintptr_t)bs->h_items};
   bool record = !(bs->exec && bs->sig == sig);
   hipStream_t s = bs->stream;
   HIP_TRY(c, hipEventRecord(bs->ev_in, (hipStream_t)stream));
@@ -303,13 +310,17 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
     hipError_t e = hipSuccess;
     auto step = [&](hipError_t r) { if (e == hipSuccess) e = r; };
     step(hipMemcpyAsync(dG, bs->h_grids, sizeof(BGrid) * count, hipMemcpyHostToDevice, s));
-    step(hipMemcpyAsync(dQ, bs->h_queue, sizeof(BQueue), hipMemcpyHostToDevice, s));
-    step(hipMemcpyAsync(dR, bs->h_items, sizeof(BItem) * total_items, hipMemcpyHostToDevice, s));
+    step(hipMemcpyAsync(dQ, bs->h_queue, 2 * sizeof(BQueue), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < 2; ++q)
+      if (items[q])
+        step(hipMemcpyAsync(dR[q], hit[q], sizeof(BItem) * items[q], hipMemcpyHostToDevice, s));
     step(launch_batch_pack(dG, count, max_n, s));
-    step(launch_batch_f64(dG, dQ, dR, waves, s));
+    if (ngrids[0])
+      step(launch_batch_f64(dG, dQ, dR[0], dQ + 1, dR[1], waves[0], false, s));
+    step(launch_batch_f64(dG, dQ + 1, dR[1], dQ + 1, dR[1], waves[1], true, s));
     step(launch_batch_unpack(dG, count, max_n, s));
     step(hipMemcpyAsync(bs->h_grids, dG, sizeof(BGrid) * count, hipMemcpyDeviceToHost, s));
-    step(hipMemcpyAsync(bs->h_queue, dQ, sizeof(BQueue), hipMemcpyDeviceToHost, s));
+    step(hipMemcpyAsync(bs->h_queue, dQ, 2 * sizeof(BQueue), hipMemcpyDeviceToHost, s));
     hipError_t e2 = hipStreamEndCapture(s, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -329,10 +340,17 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
   HIP_TRY(c, hipStreamWaitEvent((hipStream_t)stream, bs->ev_out, 0));
   HIP_TRY(c, hipStreamSynchronize(s));
 
-  if (bs->h_queue->error) return fail(c, SOR_ETIMEOUT, "a queue wait exceeded its bound");
+  for (int q = 0; q < 2; ++q)
+    if (bs->h_queue[q].error) return fail(c, SOR_ETIMEOUT, "a queue wait exceeded its bound");
   sor_status overall = SOR_OK;
+  bs->done_ms.assign(count, NAN);
+  long long t0 = 0;                       // start of the first persistent launch
+  for (int k = 0; k < 2; ++k)
+    if (bs->h_queue[k].t0 > 0 && (t0 == 0 || bs->h_queue[k].t0 < t0)) t0 = bs->h_queue[k].t0;
   for (int g = 0; g < count; ++g) {
     const BGrid &G = bs->h_grids[g];
+    if (G.t_done > 0 && t0 > 0)
+      bs->done_ms[g] = (double)(G.t_done - t0) / (double)bs->wall_khz;
     sor_result &r = results[g];
     r = sor_result{};
     r.rel_residual = NAN;
@@ -352,6 +370,14 @@ sor_status sor_batch_solve_f64(sor_ctx *c, const sor_grid_desc *grids, int32_t c
   }
   if (overall == SOR_EDEVICE) return fail(c, SOR_EDEVICE, "a grid did not finish");
   return overall;
+}
+
+sor_status sor_batch_last_times(const sor_ctx *c, int32_t count, double *done_ms) {
+  if (!c || !done_ms || count < 0) return SOR_EINVAL;
+  const std::vector<double> *v = c->batch ? &c->batch->done_ms : nullptr;
+  if (!v || (size_t)count != v->size()) return SOR_EINVAL;
+  for (int g = 0; g < count; ++g) done_ms[g] = (*v)[g];
+  return SOR_OK;
 }
 
 sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
@@ -445,7 +471,7 @@ sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *b
   std::vector<double> hb(4 * (size_t)n, 1.0);
   hipError_t he = hipMemcpy(bdy, hb.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice);
   const double omega = omega_opt(n);
-  const int iters = 96;                                 // divisible by 1, 2, 4
+  const int iters = 96;                                 // passes may end short
   std::vector<sor_grid_desc> gd((size_t)G);
   std::vector<sor_mixed_desc> md((size_t)G);
   for (long long g = 0; g < G; ++g) {
@@ -458,7 +484,11 @@ sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *b
   const auto saved = table.find(cls) != table.end() ? table[cls] : sor_tiling{0, 0};
   sor_tiling bt{4, 64};
   double best_t = INFINITY;
-  for (int T : {1, 2, 4}) {
+  // Batched FP64 passes have a fixed depth: only the tile height is searched
+  // for them.
+  const std::vector<int> depths = prec == kF64 ? std::vector<int>{kBatchT}
+                                                : std::vector<int>{2, 3, 4};
+  for (int T : depths) {
     for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384}) {
       if (he != hipSuccess) break;
       if (seg > 2 * (n + 1) && seg != 16) continue;

@@ -65,6 +65,25 @@ sor_status check_common(sor_ctx *c, const void *u, const void *bdy,
 int prec_index(int bits);
 // Young's optimal omega 2/(1 + sin(pi/(n+1))) (sor_omega_opt).
 double omega_opt(int n);
+// Inner SOR iterations per correction of the mixed-precision solves when the
+// caller passes none: n/2 rounded up to a multiple of the batched kernel's
+// fixed depth kMixTMax (at least that depth), so that batched and served
+// grids run in the fixed-depth kernel.  Measured on 4096^2 to 256^2 Poisson
+// problems, about n/2 reaches a relative residual of 1e-8 in the least time
+// (each correction then lowers the residual about 20-fold); 2n and n take
+// longer.
+inline int64_t mixed_inner_default(int n) {
+  const int64_t half = n > 1 ? (int64_t)(n / 2) : 1;
+  return (half + kMixTMax - 1) / kMixTMax * kMixTMax;
+}
+// Largest side of a mixed-precision solve with binary16 inner storage.  Above
+// it the 11-bit significand cannot hold the smooth correction: the inner
+// sweeps stop moving once the per-iteration change of a cell is below half an
+// ulp of its value, and the rounding of a smooth field is itself smooth, so
+// the correction is wrong in exactly the components SOR is slow to fix.
+// Measured: the refinement reaches 1e-8 within 30 corrections up to n = 1024
+// and stalls near a relative residual of 1e2-1e3 from n = 1536.
+constexpr int kMaxN16 = 1024;
 void batch_state_free(sor_ctx *c);
 void mix_state_free(sor_ctx *c);
 // Segment rows chosen from the grid side for one plain solve: as many tiles

@@ -131,6 +131,7 @@ struct alignas(128) BGrid {
   int64_t passes;          // passes completed (all launches)
   double stop_max;
   double last_max;         // change at the last checked iteration
+  int64_t t_done;          // device wall clock when the grid retired
   unsigned long long slots[kBSlots][kTMax];
 };
 
@@ -220,18 +221,30 @@ hipError_t launch_mix_pack(int prec_lo, const BMGrid *grids, const int *slots, i
                            int max_n, hipStream_t s);
 hipError_t launch_mix_unpack(const BMGrid *grids, const int *slots, int count,
                              int max_n, hipStream_t s);
-hipError_t launch_mix_batch(int prec_lo, BMGrid *grids, BQueue *q, BItem *ring,
+hipError_t launch_mix_batch(int prec_lo, bool dyn, BMGrid *grids, BQueue *q, BItem *ring,
                             int waves, hipStream_t s);
-int mix_waves_per_cu(int prec_lo);
+int mix_waves_per_cu(int prec_lo, bool dyn);
 
 hipError_t launch_batch_pack(BGrid *grids, int count, int max_n,
                              hipStream_t s);
 hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n,
                                hipStream_t s);
-// Persistent batched sweep (FP64 storage).  waves: persistent wavefronts.
-hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, int waves,
-                            hipStream_t s);
-int batch_waves_per_cu_f64();
+// Depth of the persistent batched FP64 sweep: the deepest pass whose tile
+// body (with a source term; grids without one read it as zero) keeps two
+// wavefronts per SIMD.  A grid's passes all have the tile geometry of this
+// depth; shorter passes (re-runs, the last iterations before a limit) run in
+// a tail kernel.
+constexpr int kBatchT = 5;
+// Deepest inner pass of the mixed-precision persistent kernel (batched solves
+// and the request server), same rule.
+constexpr int kMixTMax = 4;
+// Persistent batched sweep (FP64 storage).  The main kernel (tail false)
+// takes its items from q/ring and parks grids that need a shorter pass in
+// tq/tring; the tail kernel takes the parked passes from q/ring (pass tq = q,
+// tring = ring).  waves: persistent wavefronts.
+hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, BQueue *tq, BItem *tring,
+                            int waves, bool tail, hipStream_t s);
+int batch_waves_per_cu_f64(bool tail);
 
 // Geometry of the blocked kernel for a precision, iterations-per-pass T and
 // ordering (0: red-black, 1: four-colour): V cells per lane, S stages, H halo

@@ -137,7 +137,9 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
   double it_max[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    unsigned long long b = __hip_atomic_load(&ctl->slots[lane][t], __ATOMIC_ACQUIRE,
+    // Relaxed: the fence above already acquired (an acquire load would
+    // invalidate the XCD's L2 once per slot).
+    unsigned long long b = __hip_atomic_load(&ctl->slots[lane][t], __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&ctl->slots[lane][t], 0ull, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -293,15 +295,22 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // any iteration of the pass is non-finite when its row is stored; the maxima
 // alone would miss a NaN made from finite operands (+inf + -inf), because
 // the max drops NaN.  Non-finite inputs are caught when they are packed.
+//
+// DYN (red-black only): the tile has the geometry of depth T but applies only
+// the first s_run (even, 2..2T) half-sweeps, i.e. s_run/2 iterations; the
+// others are skipped by a wave-uniform branch, and m[t] stays 0 for the
+// iterations not applied.  The halo sized for T covers any smaller depth, so
+// the core cells get exactly the s_run/2-iteration result.
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0>
+template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0, bool DYN = false>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
-                                             bool &bad) {
+                                             bool &bad, int s_run = 2 * T) {
   using st = typename PT<P>::st;
   using ct = typename PT<P>::ct;
   constexpr int V = PT<P>::V;
   static_assert(ORD == 0 || P == kF64, "other orderings are instantiated for FP64");
+  static_assert(!DYN || ORD == 0, "a run-time depth is implemented for red-black passes");
   constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
   constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
@@ -334,8 +343,14 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   const int64_t tile_off = (int64_t)a * g.pitch + j0;
   const auto rin = make_rsrc((const st *)g.in + tile_off, extent);
   const auto rout = make_rsrc((st *)g.out + tile_off, extent);
+  // A null source reads as zeros (a resource of no records returns 0 for
+  // every load).  Adding +0 changes the neighbour sum only when it is -0, and
+  // then the update still gives the same value and change (0.25 * s - u is
+  // -u, or a zero whose sign the relaxation step loses), so a Laplace grid
+  // gets the same bits through this path as through the one without a source.
   __amdgpu_buffer_rsrc_t rf;
-  if constexpr (POIS) rf = make_rsrc((const st *)g.F + tile_off, extent);
+  if constexpr (POIS)
+    rf = g.F ? make_rsrc((const st *)g.F + tile_off, extent) : make_rsrc(g.in, 0u);
   const unsigned lane_off = (unsigned)(lane * V * ESZ);
   const unsigned st_off = lane_store ? lane_off : kDrop;
   const int from_lo = ((lane + 63) & 63) << 2;   // permute address: lane - 1
@@ -441,6 +456,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         constexpr int sq = ((i + 1 - k) % W + W) % W;
         constexpr int su = (sq + W - 1) % W;
         constexpr int sd = (sq + 1) % W;
+        if (!DYN || k == 0 || k < s_run) {
         static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
           constexpr int v = v0 + 2 * decltype(JV)::value;
           const ct self = w[sq][v];
@@ -462,6 +478,9 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
           if constexpr (v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
+        } else if constexpr (k + 1 < S) {
+          xn[k + 1] = (ct)0;                          // skipped: never read
+        }
         // Keep the exchange where it is issued (a scheduler would otherwise
         // sink it next to its use a step later and wait for it there).
         __builtin_amdgcn_sched_barrier(0);
@@ -657,9 +676,6 @@ __device__ __forceinline__ unsigned count_item_done(unsigned *counter) {
 // ---------------------------------------------------------------------------
 // Work queue of the persistent batched kernels (see BQueue / BItem).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long ld_acq(const unsigned long long *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Publish items (grid g, 0..ntiles-1) (whole wave).
 __device__ inline void bq_publish(BQueue *q, BItem *ring, int g, int ntiles) {
@@ -670,12 +686,17 @@ __device__ inline void bq_publish(BQueue *q, BItem *ring, int g, int ntiles) {
                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   base = __shfl(base, 0, 64);
   const unsigned long long gen = q->gen, mask = q->mask;
+  // Every payload, then one release fence, then every tag: a release store
+  // per item would write back the XCD's L2 once per 64 items.
   for (int i = lane; i < ntiles; i += 64) {
     const unsigned long long idx = base + (unsigned long long)i;
-    BItem *it = &ring[idx & mask];
-    __hip_atomic_store(&it->payload, ((unsigned long long)g << 32) | (unsigned)i,
+    __hip_atomic_store(&ring[idx & mask].payload, ((unsigned long long)g << 32) | (unsigned)i,
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&it->tag, bq_tag(gen, idx), __ATOMIC_RELEASE,
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  for (int i = lane; i < ntiles; i += 64) {
+    const unsigned long long idx = base + (unsigned long long)i;
+    __hip_atomic_store(&ring[idx & mask].tag, bq_tag(gen, idx), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -692,9 +713,14 @@ __device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
   BItem *it = &ring[idx & q->mask];
   const unsigned long long want = bq_tag(q->gen, idx);
   const long long t0 = wall_clock64();
+  // Poll with relaxed loads and acquire once the item is there: an acquire
+  // load at agent scope invalidates the XCD's L2 each time, which a waiting
+  // wave would otherwise do on every poll, under the working waves' feet.
+  // Waits back off from about 0.2 us to about 3 us between polls.
+  int naps = 1;
   for (;;) {
-    if (ld_acq(&it->tag) == want) break;
-    if (__hip_atomic_load(&q->remaining, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) <= 0)
+    if (__hip_atomic_load(&it->tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == want) break;
+    if (__hip_atomic_load(&q->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0)
       return false;
     if (__hip_atomic_load(&q->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       return false;
@@ -703,12 +729,16 @@ __device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
         __hip_atomic_fetch_or(&q->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
-    __builtin_amdgcn_s_sleep(8);
+    for (int k = 0; k < naps; ++k) __builtin_amdgcn_s_sleep(8);
+    naps = naps < 16 ? 2 * naps : 16;
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   const unsigned long long p = __hip_atomic_load(&it->payload, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-  g = (int)(p >> 32);
-  tile = (int)(p & 0xffffffffu);
+  // The item is the same in every lane: keep it in scalar registers, so the
+  // grid record and everything derived from it stay wave-uniform.
+  g = __builtin_amdgcn_readfirstlane((int)(p >> 32));
+  tile = __builtin_amdgcn_readfirstlane((int)(p & 0xffffffffu));
   return true;
 }
 

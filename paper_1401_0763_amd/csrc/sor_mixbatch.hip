@@ -11,9 +11,7 @@
 namespace sor {
 
 __device__ __forceinline__ int mix_depth(long long left, int T) {
-  if (T >= 4 && left >= 4) return 4;
-  if (T >= 2 && left >= 2) return 2;
-  return 1;
+  return left < T ? (int)left : T;
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -49,8 +47,10 @@ __device__ __forceinline__ typename PT<PL>::st to_lo(double x) {
 }
 
 // One row block (rows 1 + t*kMixRows ...) of the RESID, CAST or ACCUM phase.
+// Not inlined, like mix_finish: merged into the kernel's loop beside the tile
+// body they raise its register count.
 template <int PL>
-__device__ void mix_rowblock(BMGrid *G, int t, int phase) {
+__device__ __noinline__ void mix_rowblock(BMGrid *G, int t, int phase) {
   using st = typename PT<PL>::st;
   const int lane = threadIdx.x & 63;
   const int n = G->n;
@@ -95,9 +95,10 @@ __device__ void mix_rowblock(BMGrid *G, int t, int phase) {
   }
 }
 
-// One tile of a low-precision inner blocked pass on the correction.
-template <int PL, int T>
-__device__ __forceinline__ bool mix_sweep_tile(BMGrid *G, int tile) {
+// One tile of a low-precision inner blocked pass of t_run (1..T) iterations
+// (DYN; else exactly T) on the correction, in the tile geometry of depth T.
+template <int PL, int T, bool DYN>
+__device__ __forceinline__ bool mix_sweep_tile(BMGrid *G, int tile, int t_run) {
   using ct = typename PT<PL>::ct;
   constexpr int V = PT<PL>::V;
   constexpr int S = 2 * T;
@@ -117,13 +118,13 @@ __device__ __forceinline__ bool mix_sweep_tile(BMGrid *G, int tile) {
   bool bad = false;
   // The next pass's tiles and the ACCUM phase may run on other XCDs in this
   // same launch.
-  blocked_tile<PL, T, true, kCohAgent>(v, tile, m, bad);
+  blocked_tile<PL, T, true, kCohAgent, 0, DYN>(v, tile, m, bad, 2 * t_run);
   return bad;
 }
 
 // Serial step after the last item of a phase (whole wave).
 template <int PL>
-__device__ void mix_finish(BMGrid *G, int g, BQueue *q, BItem *ring) {
+__device__ __noinline__ void mix_finish(BMGrid *G, int g, BQueue *q, BItem *ring) {
   const int lane = threadIdx.x & 63;
   const int phase = G->phase;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -161,7 +162,7 @@ __device__ void mix_finish(BMGrid *G, int g, BQueue *q, BItem *ring) {
       G->cur = 0;
       G->inner_left = G->inner_iters;
       G->pass_T = mix_depth(G->inner_left, G->T);
-      nitems = blocked_ntiles(PL, G->n, G->pass_T, G->seg_rows);
+      nitems = blocked_ntiles(PL, G->n, kMixTMax, G->seg_rows);
     } else if (phase == kPhSweep) {
       G->passes += 1;
       G->cur ^= 1;
@@ -171,7 +172,7 @@ __device__ void mix_finish(BMGrid *G, int g, BQueue *q, BItem *ring) {
         done_status = 3;
       } else if (G->inner_left > 0) {
         G->pass_T = mix_depth(G->inner_left, G->T);
-        nitems = blocked_ntiles(PL, G->n, G->pass_T, G->seg_rows);
+        nitems = blocked_ntiles(PL, G->n, kMixTMax, G->seg_rows);
       } else {
         G->phase = kPhAccum;
         nitems = G->nrb;
@@ -204,7 +205,11 @@ __device__ void mix_finish(BMGrid *G, int g, BQueue *q, BItem *ring) {
   }
 }
 
-template <int PL>
+// DYN false: every inner pass has the full depth kMixTMax (each grid's inner
+// iteration count is a multiple of it), one fixed tile body, two resident
+// wavefronts per SIMD; DYN true: any inner count, passes of run-time depth,
+// one resident wavefront per SIMD.
+template <int PL, bool DYN>
 __global__ __launch_bounds__(64) void mix_batch_kernel(BMGrid *grids, BQueue *q, BItem *ring) {
   const int lane = threadIdx.x & 63;
   if (lane == 0 && blockIdx.x == 0) {
@@ -219,11 +224,8 @@ __global__ __launch_bounds__(64) void mix_batch_kernel(BMGrid *grids, BQueue *q,
     BMGrid *G = &grids[g];
     const int phase = G->phase;
     if (phase == kPhSweep) {
-      const int T = G->pass_T;
-      bool bad;
-      if (T == 4) bad = mix_sweep_tile<PL, 4>(G, item);
-      else if (T == 2) bad = mix_sweep_tile<PL, 2>(G, item);
-      else bad = mix_sweep_tile<PL, 1>(G, item);
+      const int T = DYN ? G->pass_T : kMixTMax;
+      const bool bad = mix_sweep_tile<PL, kMixTMax, DYN>(G, item, T);
       if (__ballot(bad) != 0 && lane == 0)
         __hip_atomic_fetch_or(&G->nonfinite, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -299,23 +301,33 @@ hipError_t launch_mix_unpack(const BMGrid *grids, const int *slots, int count, i
   return hipGetLastError();
 }
 
-hipError_t launch_mix_batch(int prec_lo, BMGrid *grids, BQueue *q, BItem *ring, int waves,
-                            hipStream_t s) {
-  if (prec_lo == kF32)
-    hipLaunchKernelGGL(mix_batch_kernel<kF32>, dim3(waves), dim3(64), 0, s, grids, q, ring);
+hipError_t launch_mix_batch(int prec_lo, bool dyn, BMGrid *grids, BQueue *q, BItem *ring,
+                            int waves, hipStream_t s) {
+  if (prec_lo == kF32 && !dyn)
+    hipLaunchKernelGGL((mix_batch_kernel<kF32, false>), dim3(waves), dim3(64), 0, s, grids, q, ring);
+  else if (prec_lo == kF32)
+    hipLaunchKernelGGL((mix_batch_kernel<kF32, true>), dim3(waves), dim3(64), 0, s, grids, q, ring);
+  else if (!dyn)
+    hipLaunchKernelGGL((mix_batch_kernel<kF16, false>), dim3(waves), dim3(64), 0, s, grids, q, ring);
   else
-    hipLaunchKernelGGL(mix_batch_kernel<kF16>, dim3(waves), dim3(64), 0, s, grids, q, ring);
+    hipLaunchKernelGGL((mix_batch_kernel<kF16, true>), dim3(waves), dim3(64), 0, s, grids, q, ring);
   return hipGetLastError();
 }
 
-int mix_waves_per_cu(int prec_lo) {
+int mix_waves_per_cu(int prec_lo, bool dyn) {
   int blocks = 0;
-  hipError_t e = prec_lo == kF32
-      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF32>, 64, 0)
-      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF16>, 64, 0);
+  hipError_t e;
+  if (prec_lo == kF32 && !dyn)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF32, false>, 64, 0);
+  else if (prec_lo == kF32)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF32, true>, 64, 0);
+  else if (!dyn)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF16, false>, 64, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, mix_batch_kernel<kF16, true>, 64, 0);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return 8;
+    return 4;
   }
   return blocks > 0 ? blocks : 1;
 }

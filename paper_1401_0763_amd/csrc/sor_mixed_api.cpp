@@ -92,7 +92,7 @@ void fill_slot(BMGrid &G, char *region, const SlotLayout &s, int prec_lo, int n,
   G.pitch = s.L64.pitch;
   G.lo_pitch = s.Llo.pitch;
   G.n = n;
-  G.T = t.iters_per_pass >= 4 ? 4 : t.iters_per_pass >= 2 ? 2 : 1;
+  G.T = std::max(1, std::min(t.iters_per_pass, kMixTMax));
   G.seg_rows = t.seg_rows;
   G.nrb = s.nrb;
   G.omega = omega;
@@ -101,7 +101,7 @@ void fill_slot(BMGrid &G, char *region, const SlotLayout &s, int prec_lo, int n,
   const double h = 1.0 / (double)(n + 1);
   G.target = prec_lo == kF16 ? std::ldexp(h * h, 14) / 0.0737 : 1.0;
   G.max_outer = max_outer;
-  G.inner_iters = inner_iters > 0 ? inner_iters : 2 * (int64_t)n;
+  G.inner_iters = inner_iters > 0 ? inner_iters : mixed_inner_default(n);
   G.phase = kPhResid;
   G.nitems = s.nrb;
   G.rel = NAN;
@@ -122,7 +122,8 @@ struct MixRunner {
   int *d_list = nullptr, *h_list = nullptr;     // pack / unpack slot lists
   int *d_list2 = nullptr, *h_list2 = nullptr;
   unsigned long long gen = 0;
-  int waves = 0;
+  int waves = 0;                 // persistent wavefronts of the fixed-depth kernel
+  int waves_dyn = 0;             // ... of the run-time-depth kernel
   long long wall_khz = 100000;
   hipStream_t stream = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -160,7 +161,8 @@ struct MixRunner {
       wall_khz = khz;
     int cus = 0;
     if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-    waves = std::max(1, cus) * mix_waves_per_cu(prec_lo);
+    waves = std::max(1, cus) * mix_waves_per_cu(prec_lo, false);
+    waves_dyn = std::max(1, cus) * mix_waves_per_cu(prec_lo, true);
     if (max_slots > slots_cap) {
       if (d_grids) { (void)hipFree(d_grids); d_grids = nullptr; }
       if (h_grids) { (void)hipHostFree(h_grids); h_grids = nullptr; }
@@ -182,7 +184,8 @@ struct MixRunner {
       if ((e = hipHostMalloc((void **)&h_q, sizeof(BQueue), hipHostMallocDefault)) != hipSuccess) return e;
     }
     unsigned long long cap = 1024;
-    while (cap < 2ull * (max_items_total + (unsigned long long)waves) + 1024) cap <<= 1;
+    while (cap < 2ull * (max_items_total + (unsigned long long)std::max(waves, waves_dyn)) + 1024)
+      cap <<= 1;
     if (cap > ring_cap) {
       if (d_ring) { (void)hipFree(d_ring); d_ring = nullptr; }
       if ((e = hipMalloc(&d_ring, sizeof(BItem) * cap)) != hipSuccess) return e;
@@ -197,6 +200,17 @@ struct MixRunner {
       if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
     }
     return hipSuccess;
+  }
+
+  // Kernel for a launch over the listed slots: the run-time-depth one when
+  // some grid's inner iteration count is not a multiple of the fixed depth,
+  // and for binary16 storage (whose fixed-depth kernel holds one wavefront
+  // per SIMD, the run-time-depth one two).
+  bool need_dyn(const std::vector<int> &active) const {
+    if (prec_lo == kF16) return true;
+    for (int s : active)
+      if (h_grids[s].inner_iters % kMixTMax != 0) return true;
+    return false;
   }
 
   // Queue the pending items of the listed slots (their descriptors are in
@@ -275,6 +289,9 @@ extern "C" sor_status sor_batch_solve_mixed(sor_ctx *c, const sor_mixed_desc *gr
     if (st != SOR_OK) return fail(c, st, "grid %d: %s", g, c->err.c_str());
     if (!(d.rel_tol >= 0.0) || !(d.corr_tol >= 0.0) || d.max_outer < 0)
       return fail(c, SOR_EINVAL, "grid %d: rel_tol, corr_tol or max_outer invalid", g);
+    if (plo == kF16 && d.n > kMaxN16)
+      return fail(c, SOR_EINVAL, "grid %d: binary16 inner storage supports n <= %d (n = %d)", g,
+                  kMaxN16, d.n);
   }
   MixBatchState *ms = mix_state_for(c);
   if (!ms) return fail(c, SOR_ENOMEM, "out of host memory");
@@ -291,8 +308,7 @@ extern "C" sor_status sor_batch_solve_mixed(sor_ctx *c, const sor_mixed_desc *gr
     arena += lay[g].total;
     til[g] = batch_tiling(c, plo == kF32 ? kF32 : kF16, grids[g].n);
     size_t most = (size_t)lay[g].nrb;
-    for (int t : {1, 2, 4})
-      most = std::max(most, (size_t)blocked_ntiles(plo, grids[g].n, t, til[g].seg_rows));
+    most = std::max(most, (size_t)blocked_ntiles(plo, grids[g].n, kMixTMax, til[g].seg_rows));
     max_items += most;
     max_n = std::max(max_n, grids[g].n);
   }
@@ -321,7 +337,9 @@ extern "C" sor_status sor_batch_solve_mixed(sor_ctx *c, const sor_mixed_desc *gr
     R.h_list[g] = g;
   }
   const size_t nitems = R.build_queue(order, 0);
-  const std::vector<long long> sig = {count, (long long)nitems, max_n, plo, R.waves,
+  const bool dyn = R.need_dyn(order);
+  const int nwaves = dyn ? R.waves_dyn : R.waves;
+  const std::vector<long long> sig = {count, (long long)nitems, max_n, plo, nwaves, dyn,
                                       (long long)(uintptr_t)base, (long long)R.ring_cap,
                                       (long long)(uintptr_t)R.h_items};
   hipStream_t s = R.stream;
@@ -340,7 +358,7 @@ extern "C" sor_status sor_batch_solve_mixed(sor_ctx *c, const sor_mixed_desc *gr
     step(hipMemcpyAsync(R.d_q, R.h_q, sizeof(BQueue), hipMemcpyHostToDevice, s));
     step(hipMemcpyAsync(R.d_ring, R.h_items, sizeof(BItem) * nitems, hipMemcpyHostToDevice, s));
     step(launch_mix_pack(plo, R.d_grids, R.d_list, count, max_n, s));
-    step(launch_mix_batch(plo, R.d_grids, R.d_q, R.d_ring, R.waves, s));
+    step(launch_mix_batch(plo, dyn, R.d_grids, R.d_q, R.d_ring, nwaves, s));
     step(launch_mix_unpack(R.d_grids, R.d_list, count, max_n, s));
     step(hipMemcpyAsync(R.h_grids, R.d_grids, sizeof(BMGrid) * count, hipMemcpyDeviceToHost, s));
     step(hipMemcpyAsync(R.h_q, R.d_q, sizeof(BQueue), hipMemcpyDeviceToHost, s));
@@ -553,7 +571,9 @@ void sor_server::loop() {
     const size_t nitems = run.build_queue(active, slice_ticks);
     step(hipMemcpyAsync(run.d_q, run.h_q, sizeof(BQueue), hipMemcpyHostToDevice, s));
     step(hipMemcpyAsync(run.d_ring, run.h_items, sizeof(BItem) * nitems, hipMemcpyHostToDevice, s));
-    step(launch_mix_batch(prec_lo, run.d_grids, run.d_q, run.d_ring, run.waves, s));
+    const bool dyn = run.need_dyn(active);
+    step(launch_mix_batch(prec_lo, dyn, run.d_grids, run.d_q, run.d_ring,
+                          dyn ? run.waves_dyn : run.waves, s));
     step(hipMemcpyAsync(run.h_grids, run.d_grids, sizeof(BMGrid) * max_slots, hipMemcpyDeviceToHost, s));
     step(hipMemcpyAsync(run.h_q, run.d_q, sizeof(BQueue), hipMemcpyDeviceToHost, s));
     step(hipStreamSynchronize(s));
@@ -640,8 +660,7 @@ sor_status sor_server_create(int device, int32_t inner_bits, size_t hbm_budget,
   // Ring sized for every slot holding its largest phase at once: sides up to
   // 4096 with tiles of at least kServerMinSeg rows, plus the waiting waves.
   size_t per_slot = (4096 + kMixRows - 1) / kMixRows;
-  for (int t : {1, 2, 4})
-    per_slot = std::max(per_slot, (size_t)blocked_ntiles(srv->prec_lo, 4096, t, kServerMinSeg));
+  per_slot = std::max(per_slot, (size_t)blocked_ntiles(srv->prec_lo, 4096, kMixTMax, kServerMinSeg));
   const size_t max_items = (size_t)max_slots * per_slot;
   if (srv->run.init(device, srv->prec_lo, max_slots, max_items) != hipSuccess ||
       !srv->arena.init(hbm_budget)) {
@@ -659,6 +678,7 @@ sor_status sor_server_submit(sor_server *srv, const sor_request *req, uint64_t *
   if (!srv || !req || !ticket || !req->boundary) return SOR_EINVAL;
   const int n = req->n;
   if (n < 1 || n > 4096) return SOR_EINVAL;
+  if (srv->prec_lo == kF16 && n > kMaxN16) return SOR_EINVAL;
   if (!(req->rel_tol >= 0.0) || !(req->corr_tol >= 0.0) || req->max_outer < 0) return SOR_EINVAL;
   double omega = req->omega;
   if (!(omega > 0.0)) omega = omega_opt(n);

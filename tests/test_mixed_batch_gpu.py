@@ -1,9 +1,12 @@
 """GPU parity of mixed-precision batched solves and of the request server.
 
-Each grid, whether solved in a batch or served among other requests, must
-equal the CPU oracle's defect-correction solve of that grid alone bit for bit
-at the same number of corrections (the inner sweeps, casts and corrections
-are exactly rounded; only the stopping test's norm sums differ in order)."""
+Grids and requests that pass no inner iteration count get the library's
+default (n/2 rounded up to a multiple of 4); the oracle's default is the same
+count.  Each
+grid, whether solved in a batch or served among other requests, must equal
+the CPU oracle's defect-correction solve of that grid alone bit for bit at
+the same number of corrections (the inner sweeps, casts and corrections are
+exactly rounded; only the stopping test's norm sums differ in order)."""
 import time
 
 import numpy as np
@@ -50,16 +53,20 @@ def grids_for(seed, sizes):
     return out
 
 
-@pytest.mark.parametrize("bits", [32, 16])
-def test_mixed_batch_fixed_corrections_bitwise(sor, ctx, bits):
+@pytest.mark.parametrize("bits,odd", [(32, False), (16, False), (32, True)])
+def test_mixed_batch_fixed_corrections_bitwise(sor, ctx, bits, odd):
+    """Two corrections per grid with the default inner count (a multiple of
+    the kernel's fixed depth), and with counts that are not (the run-time
+    depth kernel: 2n + 1, and 1, 2, 3 on the smallest grids)."""
     grids = grids_for(1, [1, 4, 33, 64, 100, 130, 7, 250])
     outer = 2
+    inner = [2 * g.n + 1 if g.n > 4 else g.n + 1 for g in grids] if odd else [None] * len(grids)
     us = [dev(g.u0) for g in grids]
-    specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 0.0, outer, 0)
-             for u, g in zip(us, grids)]
+    specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 0.0, outer, m or 0)
+             for u, g, m in zip(us, grids, inner)]
     res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
     for k, (g, r, u) in enumerate(zip(grids, res, us)):
-        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, outer, bits, 2 * g.n)
+        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, outer, bits, inner[k])
         assert r.outer_steps == ref.outer_steps == outer, (k, r)
         assert bitwise(u.cpu().numpy(), ref.u), (k, g.n)
         assert abs(r.rel_residual - ref.rel_residual) <= 1e-9 * ref.rel_residual + 1e-300
@@ -73,7 +80,7 @@ def test_mixed_batch_to_tolerance(sor, ctx, bits, tol):
              for u, g in zip(us, grids)]
     res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
     for k, (g, r, u) in enumerate(zip(grids, res, us)):
-        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), tol, 40, bits, 2 * g.n)
+        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), tol, 40, bits)
         assert ref.converged and r.converged, (k, r, ref.relhist)
         assert r.outer_steps == ref.outer_steps, (k, r.outer_steps, ref.outer_steps)
         assert r.rel_residual <= tol
@@ -87,7 +94,7 @@ def test_mixed_batch_correction_stop_rule(sor, ctx):
              for u, g in zip(us, grids)]
     res = sor.batch_solve_mixed(specs, 32, ctx=ctx)
     for k, (g, r, u) in enumerate(zip(grids, res, us)):
-        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, 30, 32, 2 * g.n, corr_tol=1e-8)
+        ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, 30, 32, corr_tol=1e-8)
         assert ref.converged and r.converged
         assert r.outer_steps == ref.outer_steps
         assert r.final_max_delta == ref.last_correction
@@ -127,7 +134,7 @@ def test_mixed_nonfinite_data_reported(sor, ctx, bits):
              for u, (b, f, _) in zip(us, grids)]
     res = sor.batch_solve_mixed(specs, bits, ctx=ctx)
     for k, (g, r, u) in enumerate(zip(good, res, us)):
-        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), 1e-9, 40, bits, 2 * g.n)
+        ref = oracle.mixed(g.u0, g.bdy, g.f, omega_opt(g.n), 1e-9, 40, bits)
         assert ref.converged and r.converged, (k, r)
         assert r.outer_steps == ref.outer_steps
         assert bitwise(u.cpu().numpy(), ref.u), k
@@ -160,8 +167,7 @@ def test_server_nonfinite_request_reported(sor):
         assert done[tickets[k]].status == sor.ENONFINITE, (k, done[tickets[k]].result)
     for t, g in zip([tickets[0], tickets[1], tickets[-1]], good):
         c = done[t]
-        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), 1e-9, 40, 32,
-                           2 * g.n)
+        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), 1e-9, 40, 32)
         assert c.status == sor.OK and ref.converged, (g.n, c.result)
         assert bitwise(c.u, ref.u), g.n
 
@@ -196,8 +202,7 @@ def test_server_results_equal_standalone(sor, bits):
         srv.close()
     for t, g in zip(tickets, grids):
         c = done[t]
-        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), tol, 40, bits,
-                           2 * g.n)
+        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), tol, 40, bits)
         assert c.status == sor.OK and ref.converged, (g.n, c.result)
         assert c.result.outer_steps == ref.outer_steps
         assert bitwise(c.u, ref.u), g.n
