@@ -476,8 +476,9 @@ sor_status sor_batch_solve_mixed(sor_ctx *ctx, const sor_mixed_desc *grids,
 
 /*
  * Serving: a request loop on one GPU.  Requests (host arrays, copied at
- * submission) wait in a FIFO until a slot and `hbm_budget` bytes of device
- * memory are free; admitted requests keep their whole state on the device
+ * submission) wait until a slot and enough of the `hbm_budget` bytes of
+ * device memory are free (in arrival order, except that a request that does
+ * not fit may be overtaken, see sor_server_memory); admitted requests keep their whole state on the device
  * and are advanced together by time-sliced launches of the mixed-precision
  * persistent kernel (each launch runs for about `slice_ms`, then newly
  * arrived requests join and finished ones leave: continuous batching).
@@ -523,6 +524,12 @@ sor_status sor_server_poll(sor_server *srv, uint64_t ticket, double wait_ms,
 double sor_server_clock(const sor_server *srv);
 sor_status sor_server_stats(sor_server *srv, int64_t *launches, int64_t *completed,
                             int64_t *waiting, int64_t *resident);
+/* Device memory of the request state (HOST outputs, may be NULL): the
+ * budget, the bytes resident requests hold now, and the most they ever held.
+ * Admission never lets the held bytes exceed the budget: a waiting request
+ * that does not fit is passed over by later ones that do (no head-of-line
+ * blocking), but at most 32 times, after which admission waits for it. */
+sor_status sor_server_memory(sor_server *srv, size_t *budget, size_t *in_use, size_t *peak);
 const char *sor_server_last_error(const sor_server *srv);
 /* Stop the loop (unfinished requests are dropped) and free everything. */
 void sor_server_destroy(sor_server *srv);

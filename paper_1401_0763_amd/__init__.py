@@ -165,6 +165,8 @@ def _declare(lib):
     lib.sor_server_clock.restype = dbl
     lib.sor_server_stats.argtypes = [P] + [ctypes.POINTER(i64)] * 4
     lib.sor_server_stats.restype = ctypes.c_int
+    lib.sor_server_memory.argtypes = [P] + [ctypes.POINTER(ctypes.c_size_t)] * 3
+    lib.sor_server_memory.restype = ctypes.c_int
     lib.sor_server_last_error.argtypes = [P]
     lib.sor_server_last_error.restype = ctypes.c_char_p
     lib.sor_server_destroy.argtypes = [P]
@@ -646,6 +648,12 @@ class Server:
         self.lib.sor_server_stats(self.handle, *[ctypes.byref(x) for x in v])
         return dict(launches=v[0].value, completed=v[1].value, waiting=v[2].value,
                     resident=v[3].value)
+
+    def memory(self):
+        """Device memory of request state: budget, bytes held now, most held."""
+        v = [ctypes.c_size_t() for _ in range(3)]
+        self.lib.sor_server_memory(self.handle, *[ctypes.byref(x) for x in v])
+        return dict(budget=v[0].value, in_use=v[1].value, peak=v[2].value)
 
     def error(self) -> str:
         return self.lib.sor_server_last_error(self.handle).decode()

@@ -427,6 +427,8 @@ class Arena {
   }
   char *base() const { return (char *)base_; }
   size_t size() const { return size_; }
+  size_t in_use() const { return used_; }
+  size_t peak() const { return peak_; }
   // Returns an offset, or SIZE_MAX when no free range is large enough.
   size_t alloc(size_t bytes) {
     bytes = align256(bytes);
@@ -435,6 +437,8 @@ class Arena {
         const size_t off = it->first, len = it->second;
         free_.erase(it);
         if (len > bytes) free_[off + bytes] = len - bytes;
+        used_ += bytes;
+        peak_ = std::max(peak_, used_);
         return off;
       }
     }
@@ -442,6 +446,7 @@ class Arena {
   }
   void release(size_t off, size_t bytes) {
     bytes = align256(bytes);
+    used_ -= bytes;
     auto it = free_.emplace(off, bytes).first;
     auto nx = std::next(it);
     if (nx != free_.end() && it->first + it->second == nx->first) {
@@ -460,8 +465,14 @@ class Arena {
  private:
   void *base_ = nullptr;
   size_t size_ = 0;
+  size_t used_ = 0, peak_ = 0;      // bytes held by resident requests
   std::map<size_t, size_t> free_;   // offset -> length
 };
+
+// A waiting request that does not fit may be overtaken by later ones that do
+// (no head-of-line blocking), but at most this many times: then admission
+// waits for memory to free up for it.
+constexpr int kMaxBypass = 32;
 
 struct Request {
   uint64_t ticket = 0;
@@ -473,6 +484,7 @@ struct Request {
   SlotLayout lay;
   size_t off = SIZE_MAX;
   int slot = -1;
+  int bypassed = 0;                 // later requests admitted ahead of it
   bool done = false;
   sor_result result{};
   double submit_s = 0, admit_s = 0, done_s = 0;
@@ -513,16 +525,25 @@ void sor_server::loop() {
     fresh.clear();
     {
       std::unique_lock<std::mutex> lk(mu);
-      // Admit waiting requests, in arrival order, while a slot and memory are free.
-      while (!waiting.empty()) {
-        Request *q = waiting.front();
+      // Admit waiting requests in arrival order while a slot is free; one
+      // that does not fit in the free memory is passed over by later ones
+      // that do, until it has been passed over kMaxBypass times.
+      std::vector<Request *> skipped;
+      for (auto it = waiting.begin(); it != waiting.end();) {
+        Request *q = *it;
         int slot = -1;
         for (int s = 0; s < max_slots; ++s)
           if (!resident[s]) { slot = s; break; }
         if (slot < 0) break;
         const size_t off = arena.alloc(q->lay.total);
-        if (off == SIZE_MAX) break;
-        waiting.pop_front();
+        if (off == SIZE_MAX) {
+          skipped.push_back(q);
+          if (q->bypassed >= kMaxBypass) break;
+          ++it;
+          continue;
+        }
+        it = waiting.erase(it);
+        for (Request *p : skipped) ++p->bypassed;
         q->off = off;
         q->slot = slot;
         q->admit_s = now();
@@ -748,6 +769,15 @@ sor_status sor_server_stats(sor_server *srv, int64_t *launches, int64_t *complet
   if (resident)
     *resident = (int64_t)std::count_if(srv->resident.begin(), srv->resident.end(),
                                        [](Request *q) { return q != nullptr; });
+  return SOR_OK;
+}
+
+sor_status sor_server_memory(sor_server *srv, size_t *budget, size_t *in_use, size_t *peak) {
+  if (!srv) return SOR_EINVAL;
+  std::lock_guard<std::mutex> lk(srv->mu);
+  if (budget) *budget = srv->arena.size();
+  if (in_use) *in_use = srv->arena.in_use();
+  if (peak) *peak = srv->arena.peak();
   return SOR_OK;
 }
 

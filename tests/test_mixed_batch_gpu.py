@@ -207,3 +207,41 @@ def test_server_results_equal_standalone(sor, bits):
         assert c.result.outer_steps == ref.outer_steps
         assert bitwise(c.u, ref.u), g.n
         assert c.submit_s <= c.admit_s <= c.done_s
+
+
+def test_server_admission_budget_and_no_head_of_line_blocking(sor):
+    """A budget that holds one large request or a few small ones: a large
+    request that cannot be admitted while another large one is resident does
+    not hold back the small requests submitted after it (they finish first),
+    the bytes held never exceed the budget, and every result equals the
+    oracle's standalone solve bit for bit."""
+    from paper_1401_0763_amd import Server
+    big = [random_small(800 + k, 300, with_f=True) for k in range(2)]
+    small = [random_small(810 + k, 40, with_f=True) for k in range(6)]
+    budget = 8 << 20            # one n = 300 request (5.9 MiB) and four n = 40 (0.5 MiB each)
+    srv = Server(0, inner_bits=32, hbm_budget=budget, max_slots=8, slice_ms=0.5)
+    try:
+        order = [big[0], big[1]] + small
+        tickets = [srv.submit(g.bdy, g.f, None, 0.0, 1e-9, 0.0, 40, 0) for g in order]
+        done = {}
+        t_end = time.time() + 120
+        while len(done) < len(tickets) and time.time() < t_end:
+            for t in tickets:
+                if t not in done:
+                    c = srv.poll(t, wait_ms=2.0)
+                    if c is not None:
+                        done[t] = c
+        assert len(done) == len(tickets), srv.stats()
+        mem = srv.memory()
+    finally:
+        srv.close()
+    assert mem["budget"] == budget and 0 < mem["peak"] <= budget and mem["in_use"] == 0, mem
+    # The first four small requests fit beside the first large one as soon as
+    # they arrive; the second large one waits for the first to leave.
+    second_big = done[tickets[1]]
+    assert second_big.admit_s >= done[tickets[0]].done_s - 1e-3
+    for t in tickets[2:6]:
+        assert done[t].admit_s <= second_big.admit_s, (done[t].admit_s, second_big.admit_s)
+    for t, g in zip(tickets, order):
+        ref = oracle.mixed(np.zeros((g.n, g.n)), g.bdy, g.f, omega_opt(g.n), 1e-9, 40, 32)
+        assert done[t].status == sor.OK and bitwise(done[t].u, ref.u), g.n
