@@ -482,7 +482,12 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           xn[k + 1] = (ct)0;                          // skipped: never read
         }
         // Keep the exchange where it is issued (a scheduler would otherwise
-        // sink it next to its use a step later and wait for it there).
+        // sink it next to its use a step later and wait for it there).  The
+        // full barrier is also kept for correctness: a schedule that let
+        // arithmetic cross it gave results that differed from the oracle's
+        // after hundreds of iterations on a large grid, a cause never isolated
+        // (a cross-lane read too close to the FP64 write of its source is the
+        // leading suspect), so no instruction may move across a stage.
         __builtin_amdgcn_sched_barrier(0);
       });
       } else if constexpr (ORD == 1) {
