@@ -335,6 +335,108 @@ int oracle_variant_f64(int ordering, int n, double *u, const double *bdy, const 
 }
 
 /* ------------------------------------------------------------------------ */
+/* FP64 block-parallel SOR                                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Block-parallel SOR, the third parallel SOR form Sec. 3.1 names (with a
+ * citation only; no definition is given).  Reading used here: the n x n
+ * interior is cut into blocks of br rows and bc columns, aligned at interior
+ * cell (1, 1) (the last block row and column may be shorter); in every
+ * iteration all blocks are updated at the same time, each by one red-black
+ * SOR iteration of its own cells (red first, same colouring, Gauss-Seidel
+ * value and increment form of Eq. 1 as oracle_sor_f64), in which a neighbour
+ * that lies in another block is always taken at the previous iterate.  So
+ * the red half-sweep is the red-black one (a red cell's neighbours are black
+ * and still hold the previous iterate), and a black cell reads the new value
+ * of a red neighbour in its own block and the old value of one across a
+ * block edge.  Boundary values never change, so either copy serves them.
+ *
+ * One block of at least n x n cells is red-black SOR; blocks of one cell are
+ * the over-relaxed Jacobi iteration (every neighbour from the previous
+ * iterate).  Same stopping rule (Algorithm 1) and outputs as oracle_sor_f64.
+ */
+
+/* Block coordinate of interior index i (1..n) for blocks of b cells. */
+static int orc_block_of(int i, int b) { return (i - 1) / b; }
+
+/* One block-parallel iteration of U in place; P receives the previous
+ * iterate first.  Returns the max |new - old| over all updated cells. */
+static double orc_blockpar_iter_f64(int n, double *U, double *P, const double *F, double w,
+                                    int br, int bc, int *bad)
+{
+    size_t cells = (size_t)(n + 2) * (size_t)(n + 2);
+    memcpy(P, U, sizeof(double) * cells);
+    double m = orc_half_sweep_f64(n, U, F, w, 0, 1, n, bad);   /* red: as red-black */
+    for (int i = 1; i <= n; ++i) {
+        int j0 = 1 + (i & 1);                  /* first black column: (i + j) odd */
+        for (int j = j0; j <= n; j += 2) {
+            int bi = orc_block_of(i, br), bj = orc_block_of(j, bc);
+            /* a neighbour in this block: its current value; else: previous */
+            double nn = (i - 1 >= 1 && orc_block_of(i - 1, br) == bi) ? U[AT(i - 1, j)]
+                                                                       : P[AT(i - 1, j)];
+            double ss = (i + 1 <= n && orc_block_of(i + 1, br) == bi) ? U[AT(i + 1, j)]
+                                                                      : P[AT(i + 1, j)];
+            double ww = (j - 1 >= 1 && orc_block_of(j - 1, bc) == bj) ? U[AT(i, j - 1)]
+                                                                       : P[AT(i, j - 1)];
+            double ee = (j + 1 <= n && orc_block_of(j + 1, bc) == bj) ? U[AT(i, j + 1)]
+                                                                      : P[AT(i, j + 1)];
+            double old = U[AT(i, j)];
+            double s = (nn + ss) + (ww + ee);
+            if (F) s = s + F[AT(i, j)];
+            double dg = fma(0.25, s, -old);
+            double nu = fma(w, dg, old);
+            double d = fabs(nu - old);
+            if (!isfinite(nu)) *bad = 1;
+            if (d > m) m = d;
+            U[AT(i, j)] = nu;
+        }
+    }
+    return m;
+}
+
+int oracle_blockpar_f64(int n, double *u, const double *bdy, const double *f, double omega,
+                        int block_rows, int block_cols, double tol, int64_t max_iters,
+                        int64_t check_every, int64_t *iters_out, double *max_out,
+                        double *mhist)
+{
+    if (n < 1 || !u || !bdy || !(omega > 0.0 && omega < 2.0) || block_rows < 1 ||
+        block_cols < 1 || !(tol >= 0.0) || max_iters < 1 || check_every < 1)
+        return ORC_EINVAL;
+    size_t cells = (size_t)(n + 2) * (size_t)(n + 2);
+    double *U = malloc(sizeof(double) * cells);
+    double *P = malloc(sizeof(double) * cells);
+    double *F = orc_make_F(n, f);
+    if (!U || !P || (f && !F)) {
+        free(U); free(P); free(F);
+        return ORC_ENOMEM;
+    }
+    orc_fill_f64(n, U, u, bdy);
+
+    int status = ORC_NOT_CONVERGED;
+    int64_t it = 0;
+    double last = NAN;
+    for (it = 1; it <= max_iters; ++it) {
+        int bad = 0;
+        double m = orc_blockpar_iter_f64(n, U, P, F, omega, block_rows, block_cols, &bad);
+        if (mhist) mhist[it - 1] = m;
+        if (bad) { status = ORC_ENONFINITE; last = m; break; }
+        if (it % check_every == 0 || it == max_iters) {
+            last = m;
+            if (m < tol) { status = ORC_OK; break; }
+        }
+    }
+    if (it > max_iters) it = max_iters;
+    orc_extract_f64(n, U, u);
+    if (iters_out) *iters_out = it;
+    if (max_out) *max_out = last;
+    free(U);
+    free(P);
+    free(F);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* FP64 residual of the discrete system                                      */
 /* ------------------------------------------------------------------------ */
 
