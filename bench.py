@@ -500,27 +500,40 @@ def form_3d(sor, ctx, torch, n=256, iters=1000, cpu=True):
 
 
 def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
-    """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1): update rate
-    on the 4096^2 bench grid (fixed iterations, kernel time from HIP events
-    around each run of passes; 16 algorithmic bytes per update against
-    the 8 TB/s HBM peak), and iterations to 1e-8 (checked every 10) on a
-    128^2 grid next to red-black, all at their best omega (Jacobi: 1).
-    Both run their blocked passes of several iterations each (Jacobi 8,
-    four-colour 5 by default)."""
+    """The Jacobi and four-colour orderings (Sec. 2.1, Sec. 3.1) and
+    block-parallel SOR (Sec. 3.1; 128 x 128 blocks on the 4096^2 grid, 32 x
+    32 on the 128^2 one): update rate on the 4096^2 bench grid (fixed
+    iterations, kernel time from HIP events around each run of passes; 16
+    algorithmic bytes per update against the 8 TB/s HBM peak), and
+    iterations to 1e-8 (checked every 10) on a 128^2 grid next to red-black,
+    each at its best omega (Jacobi: 1; block-parallel: 1.45, the best of a
+    0.05 grid on the oracle, since it diverges from about 1.48 on).  All run
+    their blocked passes of several iterations each (Jacobi 8, four-colour
+    5, block-parallel 5 by default)."""
     from workloads import laplace_random_boundary
     g = laplace_random_boundary(n)
     b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
     out = {"workload": f"laplace_random_boundary_{n}, {iters} iterations; "
                        f"laplace_random_boundary_{n_conv} to 1e-8"}
-    for ordering, name, omega in ((sor.ORDER_JACOBI, "jacobi", 1.0),
-                                  (sor.ORDER_FOUR_COLOUR, "four_colour", g.omega)):
+    bp_big, bp_small, bp_omega = 128, 32, 1.45
+
+    def solve(name, u, bdy, omega, tol, it):
+        if name == "block_parallel":
+            blk = bp_big if u.shape[0] == n else bp_small
+            return sor.solve_blockpar_f64(u, bdy, blk, blk, None, omega, tol, it, 10, ctx=ctx)
+        ordering = {"jacobi": sor.ORDER_JACOBI, "four_colour": sor.ORDER_FOUR_COLOUR,
+                    "red_black": sor.ORDER_RED_BLACK}[name]
+        return sor.solve_variant_f64(ordering, u, bdy, None, omega, tol, it, 10, ctx=ctx)
+
+    rate_cases = (("jacobi", 1.0), ("four_colour", g.omega), ("block_parallel", 1.0))
+    for name, omega in rate_cases:
         u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
-        sor.solve_variant_f64(ordering, u, b, None, omega, 0.0, 10, 10, ctx=ctx)
+        solve(name, u, b, omega, 0.0, 10)
         u.zero_()
         ctx.set_profiling(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sor.solve_variant_f64(ordering, u, b, None, omega, 0.0, iters, 10, ctx=ctx)
+        r = solve(name, u, b, omega, 0.0, iters)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         kern_ms, launches = ctx.profile()
@@ -533,27 +546,32 @@ def form_variants(sor, ctx, torch, n=4096, iters=200, n_conv=128, cpu=True):
                      "hbm_equiv_GBs": round(BYTES_PER_LUP_F64 * n * n / (it_us * 1e-6) / 1e9, 1),
                      "hbm_frac": round(BYTES_PER_LUP_F64 * n * n / (it_us * 1e-6) / 1e9
                                        / HBM_PEAK_GBS, 3)}
+    out["block_parallel"]["blocks"] = [bp_big, bp_big]
+    out["block_parallel"]["tiling"] = list(ctx.get_variant_tiling(sor.ORDER_BLOCK_PARALLEL))
     gc = laplace_random_boundary(n_conv)
     bc = torch.tensor(gc.bdy, dtype=torch.float64, device="cuda")
     conv = {}
-    for ordering, name, omega in ((sor.ORDER_RED_BLACK, "red_black", gc.omega),
-                                  (sor.ORDER_FOUR_COLOUR, "four_colour", gc.omega),
-                                  (sor.ORDER_JACOBI, "jacobi", 1.0)):
+    for name, omega in (("red_black", gc.omega), ("four_colour", gc.omega), ("jacobi", 1.0),
+                        ("block_parallel", bp_omega)):
         u = torch.zeros((n_conv, n_conv), dtype=torch.float64, device="cuda")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = sor.solve_variant_f64(ordering, u, bc, None, omega, 1e-8, 1000000, 10, ctx=ctx)
+        r = solve(name, u, bc, omega, 1e-8, 1000000)
         torch.cuda.synchronize()
         conv[name] = {"converged": bool(r.converged), "iterations": r.iterations,
-                      "secs": round(time.perf_counter() - t0, 3)}
+                      "secs": round(time.perf_counter() - t0, 3), "omega": round(omega, 4)}
+    conv["block_parallel"]["blocks"] = [bp_small, bp_small]
     out["to_1e-8"] = conv
     if cpu:
         import oracle
         iters_cpu = 8
-        for ordering, name, omega in ((sor.ORDER_JACOBI, "jacobi", 1.0),
-                                      (sor.ORDER_FOUR_COLOUR, "four_colour", g.omega)):
+        for name, omega in rate_cases:
             t0 = time.perf_counter()
-            oracle.variant_f64(ordering, g.u0, g.bdy, None, omega, 0.0, iters_cpu, 10)
+            if name == "block_parallel":
+                oracle.blockpar_f64(g.u0, g.bdy, None, omega, bp_big, bp_big, 0.0, iters_cpu, 10)
+            else:
+                ordering = oracle.ORDER_JACOBI if name == "jacobi" else oracle.ORDER_FOUR_COLOUR
+                oracle.variant_f64(ordering, g.u0, g.bdy, None, omega, 0.0, iters_cpu, 10)
             dt = time.perf_counter() - t0
             out[name]["cpu_oracle"] = {"glups": round(n * n * iters_cpu / dt / 1e9, 3),
                                        "cores": 1,

@@ -245,11 +245,16 @@ sor_status sor_solve3d_f64(sor_ctx *ctx, double *u, const double *boundary,
  * SOR that Sec. 3.1 names, with colour(i, j) = 2 (i mod 2) + (j mod 2) on the
  * full array (boundary at index 0) and the colours swept in the order
  * 0, 1, 2, 3 (colours 1 and 2 never touch, so they are swept together).
+ * BLOCK_PARALLEL is the block-parallel SOR that Sec. 3.1 names (solved by
+ * sor_solve_blockpar_f64, which takes the block shape; the ordering value
+ * selects its tiling in sor_ctx_set_variant_tiling, and sor_solve_variant_f64
+ * rejects it with SOR_EINVAL).
  */
 enum {
   SOR_ORDER_RED_BLACK = 0,
   SOR_ORDER_JACOBI = 1,
-  SOR_ORDER_FOUR_COLOUR = 2
+  SOR_ORDER_FOUR_COLOUR = 2,
+  SOR_ORDER_BLOCK_PARALLEL = 3
 };
 
 /*
@@ -272,15 +277,48 @@ sor_status sor_solve_variant_f64(sor_ctx *ctx, int32_t ordering, double *u,
                                  int64_t check_every, void *stream, sor_result *out,
                                  double *max_hist);
 
-/* Tiling of the blocked kernel of ordering SOR_ORDER_FOUR_COLOUR or
- * SOR_ORDER_JACOBI (SOR_ORDER_RED_BLACK uses sor_ctx_set_tiling; others:
- * SOR_EINVAL).  iters_per_pass in 1..5 for FOUR_COLOUR (each is 3 colour
- * sweeps, so 5 has 15 stages, about the stage depth of red-black's 7) and
- * 1..8 for JACOBI (one sweep each); seg_rows even in 8..1024; 0 in a field
- * means "keep".  A new context uses 5 (FOUR_COLOUR) and 8 (JACOBI) and picks
- * seg_rows from the grid side as sor_ctx_set_tiling describes.  Results do
- * not depend on the tiling.  sor_ctx_get_variant_tiling reports the setting
- * (seg_rows 0 until one is set). */
+/*
+ * Block-parallel SOR (Sec. 3.1 names it, citing it without a definition;
+ * this is the reading the library implements).  The n x n interior is cut
+ * into blocks of block_rows x block_cols cells, aligned at interior cell
+ * (1, 1) (the last block row and column may be shorter).  One iteration
+ * updates every block at once by one red-black iteration of its own cells
+ * (red first, same colouring, update expression and increment form of Eq. 1
+ * as sor_solve_f64), in which a neighbour lying in another block is always
+ * taken at the previous iterate: red cells therefore get the red-black
+ * update, and a black cell reads the new value of a red neighbour in its own
+ * block and the old value of one across a block edge.  Blocks of at least
+ * n x n give sor_solve_f64's iterates bit for bit, blocks of 1 x 1 the
+ * over-relaxed Jacobi ones (SOR_ORDER_JACOBI).  Unlike red-black SOR the
+ * iteration does not converge for every omega in (0, 2): the bound depends
+ * on the block shape (n = 12, 5 x 3 blocks: converges at 1.35, diverges at
+ * 1.5); a diverging solve ends with SOR_ENONFINITE or SOR_NOT_CONVERGED like
+ * any other.
+ *
+ * Arguments, layout, ownership, stopping rule (Algorithm 1), results and
+ * errors as sor_solve_f64, plus block_rows, block_cols >= 1 (larger than n
+ * is allowed; else SOR_EINVAL).  Always runs the blocked kernel (ping-pong
+ * between two padded grids, iterations per pass from
+ * sor_ctx_set_variant_tiling with SOR_ORDER_BLOCK_PARALLEL), whatever
+ * sor_ctx_set_kernel selected; results do not depend on the tiling.
+ */
+sor_status sor_solve_blockpar_f64(sor_ctx *ctx, double *u, const double *boundary,
+                                  const double *rhs, int32_t n, double omega,
+                                  int32_t block_rows, int32_t block_cols, double tol,
+                                  int64_t max_iters, int64_t check_every, void *stream,
+                                  sor_result *out, double *max_hist);
+
+/* Tiling of the blocked kernel of ordering SOR_ORDER_FOUR_COLOUR,
+ * SOR_ORDER_JACOBI or SOR_ORDER_BLOCK_PARALLEL (SOR_ORDER_RED_BLACK uses
+ * sor_ctx_set_tiling; others: SOR_EINVAL).  iters_per_pass in 1..5 for
+ * FOUR_COLOUR (each is 3 colour sweeps, so 5 has 15 stages, about the stage
+ * depth of red-black's 7) and 1..8 for JACOBI (one sweep each) and
+ * BLOCK_PARALLEL (two half-sweeps each); seg_rows even in 8..1024; 0 in a
+ * field means "keep".  A new context uses 5 (FOUR_COLOUR), 8 (JACOBI) and 5
+ * (BLOCK_PARALLEL) and picks seg_rows from the grid side as
+ * sor_ctx_set_tiling describes.  Results do not depend on the tiling.
+ * sor_ctx_get_variant_tiling reports the setting (seg_rows 0 until one is
+ * set). */
 sor_status sor_ctx_set_variant_tiling(sor_ctx *ctx, int32_t ordering, const sor_tiling *t);
 sor_status sor_ctx_get_variant_tiling(const sor_ctx *ctx, int32_t ordering, sor_tiling *t);
 

@@ -129,6 +129,9 @@ def _declare(lib):
     lib.sor_batch_last_times.restype = ctypes.c_int
     lib.sor_solve_variant_f64.argtypes = [P, i32] + solve_args[1:]
     lib.sor_solve_variant_f64.restype = ctypes.c_int
+    lib.sor_solve_blockpar_f64.argtypes = [P, P, P, P, i32, dbl, i32, i32, dbl, i64, i64, P,
+                                           ctypes.POINTER(_Result), P]
+    lib.sor_solve_blockpar_f64.restype = ctypes.c_int
     lib.sor_ctx_set_variant_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
     lib.sor_ctx_set_variant_tiling.restype = ctypes.c_int
     lib.sor_ctx_get_variant_tiling.argtypes = [P, i32, ctypes.POINTER(_Tiling)]
@@ -287,8 +290,8 @@ class Context:
         return t.iters_per_pass, t.seg_rows
 
     def set_variant_tiling(self, ordering: int, iters_per_pass: int = 0, seg_rows: int = 0):
-        """Tiling of the blocked kernel of ORDER_FOUR_COLOUR or ORDER_JACOBI
-        (0 keeps a field)."""
+        """Tiling of the blocked kernel of ORDER_FOUR_COLOUR, ORDER_JACOBI or
+        ORDER_BLOCK_PARALLEL (0 keeps a field)."""
         t = _Tiling(int(iters_per_pass), int(seg_rows))
         self._check(self.lib.sor_ctx_set_variant_tiling(self.handle, int(ordering),
                                                         ctypes.byref(t)))
@@ -450,7 +453,7 @@ def solve_f32(u, boundary, rhs=None, omega=None, tol=1e-5, max_iters=100000,
                         omega, tol, max_iters, check_every, hist, ctx)
 
 
-ORDER_RED_BLACK, ORDER_JACOBI, ORDER_FOUR_COLOUR = 0, 1, 2
+ORDER_RED_BLACK, ORDER_JACOBI, ORDER_FOUR_COLOUR, ORDER_BLOCK_PARALLEL = 0, 1, 2, 3
 
 
 def solve_variant_f64(ordering, u, boundary, rhs=None, omega=None, tol=1e-8,
@@ -472,6 +475,31 @@ def solve_variant_f64(ordering, u, boundary, rhs=None, omega=None, tol=1e-8,
                                        float(omega), float(tol), int(max_iters),
                                        int(check_every), _stream_handle(u),
                                        ctypes.byref(res), hbuf)
+    ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
+    h = list(hbuf[: res.iterations]) if hist else None
+    return _result(st, res, h)
+
+
+def solve_blockpar_f64(u, boundary, block_rows, block_cols, rhs=None, omega=1.0, tol=1e-8,
+                       max_iters=100000, check_every=1, hist=False,
+                       ctx: Context | None = None) -> Result:
+    """FP64 block-parallel SOR in place on u: blocks of block_rows x
+    block_cols interior cells, each updated per iteration by one red-black
+    iteration with neighbours in other blocks at the previous iterate;
+    otherwise as solve_f64.  The default omega is 1 (the method does not
+    converge for every omega in (0, 2))."""
+    import torch
+    n = u.shape[0]
+    pu = _check_tensor("u", u, torch.float64, (n, n))
+    pb = _check_tensor("boundary", boundary, torch.float64, (4 * n,))
+    pf = None if rhs is None else _check_tensor("rhs", rhs, torch.float64, (n, n))
+    ctx = ctx or context(u.device.index)
+    res = _Result()
+    hbuf = (ctypes.c_double * int(max_iters))() if hist else None
+    st = ctx.lib.sor_solve_blockpar_f64(ctx.handle, pu, pb, pf, int(n), float(omega),
+                                        int(block_rows), int(block_cols), float(tol),
+                                        int(max_iters), int(check_every), _stream_handle(u),
+                                        ctypes.byref(res), hbuf)
     ctx._check(st, (OK, NOT_CONVERGED, ENONFINITE))
     h = list(hbuf[: res.iterations]) if hist else None
     return _result(st, res, h)

@@ -160,9 +160,14 @@ sor_status prof_events(sor_ctx *c, size_t k, hipEvent_t *a, hipEvent_t *b) {
 }
 
 // Pass ordering of the blocked tile for a solve ordering (1 four-colour,
-// 2 Jacobi), or -1.
+// 2 Jacobi, 3 block-parallel), or -1.
 int pass_ordering(int32_t ordering) {
-  return ordering == SOR_ORDER_FOUR_COLOUR ? 1 : ordering == SOR_ORDER_JACOBI ? 2 : -1;
+  switch (ordering) {
+    case SOR_ORDER_FOUR_COLOUR: return 1;
+    case SOR_ORDER_JACOBI: return 2;
+    case SOR_ORDER_BLOCK_PARALLEL: return 3;
+  }
+  return -1;
 }
 
 // Tiling of a four-colour or Jacobi solve (pass ordering ord): the context's
@@ -173,7 +178,8 @@ sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
   return t;
 }
 
-// Run SOR sweeps (red-black; four-colour with ord 1 or Jacobi with ord 2 on
+// Run SOR sweeps (red-black; four-colour with ord 1, Jacobi with ord 2 or
+// block-parallel red-black with ord 3 and blocks of shape bs on
 // FP64 grids, where the simple kernel is the in-place four-colour one) on the
 // packed grids A/B (same layout L) until the stopping rule or max_iters.  On
 // return *result_grid is the grid holding the final iterate.  hist (host, may
@@ -181,11 +187,13 @@ sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
 sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
                       const void *F, double omega, const Sched &sc,
                       hipStream_t s, sor_result *res, double *hist,
-                      void **result_grid, int ord, Ctl *ctl) {
+                      void **result_grid, int ord, Ctl *ctl,
+                      const BlockShape &bs = BlockShape{}) {
   HIP_TRY(c, launch_ctl_reset(ctl, s));
   const sor_tiling tl = ord ? variant_tiling(c, ord, L.n, F != nullptr)
                             : tuned_tiling(c, prec, L.n, F != nullptr);
-  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2;   // Jacobi: ping-pong only
+  // Jacobi and block-parallel passes read the previous iterate: ping-pong only.
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2 && ord != 3;
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 
@@ -220,7 +228,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       } else if (simple) {
         HIP_TRY(c, launch_simple_iteration(prec, v, ctl, sc, s));
       } else {
-        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord));
+        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord, bs));
         std::swap(cur, oth);
       }
       recs[nrecs++] = PassRec{v.in, v.out, done, Tp};
@@ -283,7 +291,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
           GridView v = view_for(base, prec, t, ord);
           v.in = src;
           v.out = dst;
-          HIP_TRY(c, launch_blocked_pass(prec, t, v, rctl, tentative ? rsc : sc, s, ord));
+          HIP_TRY(c, launch_blocked_pass(prec, t, v, rctl, tentative ? rsc : sc, s, ord, bs));
           ++reruns;
           *result_grid = dst;
           std::swap(src, dst);
@@ -672,17 +680,14 @@ sor_status sor_solve3d_f64(sor_ctx *c, double *u, const double *bdy, const doubl
   return st;
 }
 
-sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const double *bdy,
-                                 const double *rhs, int32_t n, double omega, double tol,
-                                 int64_t max_iters, int64_t check_every, void *stream,
-                                 sor_result *out, double *hist) {
-  if (!c) return SOR_EINVAL;
-  c->err.clear();
-  if (ordering == SOR_ORDER_RED_BLACK)
-    return sor_solve_f64(c, u, bdy, rhs, n, omega, tol, max_iters, check_every, stream, out,
-                         hist);
-  if (ordering != SOR_ORDER_JACOBI && ordering != SOR_ORDER_FOUR_COLOUR)
-    return fail(c, SOR_EINVAL, "unknown ordering %d", ordering);
+namespace {
+
+// Jacobi, four-colour or block-parallel solve (arguments checked except the
+// ordering's own): pack, run, unpack.
+sor_status solve_ordered(sor_ctx *c, int32_t ordering, double *u, const double *bdy,
+                         const double *rhs, int32_t n, double omega, int32_t blk_rows,
+                         int32_t blk_cols, double tol, int64_t max_iters,
+                         int64_t check_every, void *stream, sor_result *out, double *hist) {
   sor_status st = check_common(c, u, bdy, rhs, n, omega);
   if (st != SOR_OK) return st;
   if (!out) return fail(c, SOR_EINVAL, "out must not be NULL");
@@ -714,13 +719,47 @@ sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const 
     res_grid = (out->passes & 1) ? B : A;
   } else {
     st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid,
-                    pass_ordering(ordering), ctl);
+                    pass_ordering(ordering), ctl, BlockShape{blk_rows, blk_cols});
   }
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));
     HIP_TRY(c, hipStreamSynchronize(s));
   }
   return st;
+}
+
+}  // namespace
+
+sor_status sor_solve_variant_f64(sor_ctx *c, int32_t ordering, double *u, const double *bdy,
+                                 const double *rhs, int32_t n, double omega, double tol,
+                                 int64_t max_iters, int64_t check_every, void *stream,
+                                 sor_result *out, double *hist) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (ordering == SOR_ORDER_RED_BLACK)
+    return sor_solve_f64(c, u, bdy, rhs, n, omega, tol, max_iters, check_every, stream, out,
+                         hist);
+  if (ordering == SOR_ORDER_BLOCK_PARALLEL)
+    return fail(c, SOR_EINVAL, "the block-parallel ordering needs a block shape: "
+                "use sor_solve_blockpar_f64");
+  if (ordering != SOR_ORDER_JACOBI && ordering != SOR_ORDER_FOUR_COLOUR)
+    return fail(c, SOR_EINVAL, "unknown ordering %d", ordering);
+  return solve_ordered(c, ordering, u, bdy, rhs, n, omega, 1, 1, tol, max_iters, check_every,
+                       stream, out, hist);
+}
+
+sor_status sor_solve_blockpar_f64(sor_ctx *c, double *u, const double *bdy, const double *rhs,
+                                  int32_t n, double omega, int32_t block_rows,
+                                  int32_t block_cols, double tol, int64_t max_iters,
+                                  int64_t check_every, void *stream, sor_result *out,
+                                  double *hist) {
+  if (!c) return SOR_EINVAL;
+  c->err.clear();
+  if (block_rows < 1 || block_cols < 1)
+    return fail(c, SOR_EINVAL, "block shape %d x %d: both sides must be >= 1", block_rows,
+                block_cols);
+  return solve_ordered(c, SOR_ORDER_BLOCK_PARALLEL, u, bdy, rhs, n, omega, block_rows,
+                       block_cols, tol, max_iters, check_every, stream, out, hist);
 }
 
 sor_status sor_ctx_set_variant_tiling(sor_ctx *c, int32_t ordering, const sor_tiling *t) {

@@ -3,6 +3,7 @@
 
 namespace sor {
 template hipError_t launch_blocked_PT<kF64, 2, 2>(const GridView &, Ctl *,
-                                                 const Sched &, hipStream_t);
+                                                 const Sched &, hipStream_t,
+                                                 const BlockShape &);
 template int blocked_blocks_per_cu<kF64, 2, 2>(bool);
 }  // namespace sor

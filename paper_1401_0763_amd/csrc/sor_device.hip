@@ -342,7 +342,7 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
 // The blocked passes are instantiated in the sor_blocked_*_t*.hip units.
 #define SOR_EXTERN_BLOCKED(P, T)                                               \
   extern template hipError_t launch_blocked_PT<P, T>(                          \
-      const GridView &, Ctl *, const Sched &, hipStream_t);                    \
+      const GridView &, Ctl *, const Sched &, hipStream_t, const BlockShape &); \
   extern template int blocked_blocks_per_cu<P, T>(bool);
 #define SOR_EXTERN_BLOCKED_ALL(P)                                              \
   SOR_EXTERN_BLOCKED(P, 1) SOR_EXTERN_BLOCKED(P, 2) SOR_EXTERN_BLOCKED(P, 3)   \
@@ -353,7 +353,7 @@ SOR_EXTERN_BLOCKED_ALL(kF32)
 SOR_EXTERN_BLOCKED_ALL(kF16)
 #define SOR_EXTERN_BLOCKED_ORD(T, ORD)                                         \
   extern template hipError_t launch_blocked_PT<kF64, T, ORD>(                  \
-      const GridView &, Ctl *, const Sched &, hipStream_t);                    \
+      const GridView &, Ctl *, const Sched &, hipStream_t, const BlockShape &); \
   extern template int blocked_blocks_per_cu<kF64, T, ORD>(bool);
 SOR_EXTERN_BLOCKED_ORD(1, 1) SOR_EXTERN_BLOCKED_ORD(2, 1)
 SOR_EXTERN_BLOCKED_ORD(3, 1) SOR_EXTERN_BLOCKED_ORD(4, 1) SOR_EXTERN_BLOCKED_ORD(5, 1)
@@ -361,26 +361,30 @@ SOR_EXTERN_BLOCKED_ORD(1, 2) SOR_EXTERN_BLOCKED_ORD(2, 2)
 SOR_EXTERN_BLOCKED_ORD(3, 2) SOR_EXTERN_BLOCKED_ORD(4, 2)
 SOR_EXTERN_BLOCKED_ORD(5, 2) SOR_EXTERN_BLOCKED_ORD(6, 2)
 SOR_EXTERN_BLOCKED_ORD(7, 2) SOR_EXTERN_BLOCKED_ORD(8, 2)
+SOR_EXTERN_BLOCKED_ORD(1, 3) SOR_EXTERN_BLOCKED_ORD(2, 3)
+SOR_EXTERN_BLOCKED_ORD(3, 3) SOR_EXTERN_BLOCKED_ORD(4, 3)
+SOR_EXTERN_BLOCKED_ORD(5, 3) SOR_EXTERN_BLOCKED_ORD(6, 3)
+SOR_EXTERN_BLOCKED_ORD(7, 3) SOR_EXTERN_BLOCKED_ORD(8, 3)
 
 // Passes of the other orderings (FP64 only).
 template <int ORD>
 static hipError_t launch_blocked_ord(int T, const GridView &v, Ctl *ctl, const Sched &sc,
-                                     hipStream_t s) {
+                                     hipStream_t s, const BlockShape &bs) {
   switch (T) {
-    case 1: return launch_blocked_PT<kF64, 1, ORD>(v, ctl, sc, s);
-    case 2: return launch_blocked_PT<kF64, 2, ORD>(v, ctl, sc, s);
-    case 3: return launch_blocked_PT<kF64, 3, ORD>(v, ctl, sc, s);
-    case 4: return launch_blocked_PT<kF64, 4, ORD>(v, ctl, sc, s);
+    case 1: return launch_blocked_PT<kF64, 1, ORD>(v, ctl, sc, s, bs);
+    case 2: return launch_blocked_PT<kF64, 2, ORD>(v, ctl, sc, s, bs);
+    case 3: return launch_blocked_PT<kF64, 3, ORD>(v, ctl, sc, s, bs);
+    case 4: return launch_blocked_PT<kF64, 4, ORD>(v, ctl, sc, s, bs);
   }
   if constexpr (ORD == 1) {
-    if (T == 5) return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s);
+    if (T == 5) return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s, bs);
   }
-  if constexpr (ORD == 2) {
+  if constexpr (ORD == 2 || ORD == 3) {
     switch (T) {
-      case 5: return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s);
-      case 6: return launch_blocked_PT<kF64, 6, ORD>(v, ctl, sc, s);
-      case 7: return launch_blocked_PT<kF64, 7, ORD>(v, ctl, sc, s);
-      case 8: return launch_blocked_PT<kF64, 8, ORD>(v, ctl, sc, s);
+      case 5: return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s, bs);
+      case 6: return launch_blocked_PT<kF64, 6, ORD>(v, ctl, sc, s, bs);
+      case 7: return launch_blocked_PT<kF64, 7, ORD>(v, ctl, sc, s, bs);
+      case 8: return launch_blocked_PT<kF64, 8, ORD>(v, ctl, sc, s, bs);
     }
   }
   return hipErrorInvalidValue;
@@ -397,7 +401,7 @@ static int blocked_blocks_per_cu_ord(int T, bool pois) {
   if constexpr (ORD == 1) {
     if (T == 5) return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
   }
-  if constexpr (ORD == 2) {
+  if constexpr (ORD == 2 || ORD == 3) {
     switch (T) {
       case 5: return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
       case 6: return blocked_blocks_per_cu<kF64, 6, ORD>(pois);
@@ -442,7 +446,12 @@ static int blocked_blocks_per_cu_P(int T, bool pois) {
 int blocked_blocks_per_cu(int prec, int T, bool pois, int ord) {
   if (ord) {
     if (prec != kF64) return 0;
-    return ord == 1 ? blocked_blocks_per_cu_ord<1>(T, pois) : blocked_blocks_per_cu_ord<2>(T, pois);
+    switch (ord) {
+      case 1: return blocked_blocks_per_cu_ord<1>(T, pois);
+      case 2: return blocked_blocks_per_cu_ord<2>(T, pois);
+      case 3: return blocked_blocks_per_cu_ord<3>(T, pois);
+    }
+    return 0;
   }
   switch (prec) {
     case kF64: return blocked_blocks_per_cu_P<kF64>(T, pois);
@@ -461,10 +470,16 @@ bool blocked_ord_T_supported(int ord, int T) {
 }
 
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, hipStream_t s, int ord) {
+                               const Sched &sc, hipStream_t s, int ord,
+                               const BlockShape &bs) {
   if (ord) {
     if (prec != kF64) return hipErrorInvalidValue;
-    return ord == 1 ? launch_blocked_ord<1>(T, v, ctl, sc, s) : launch_blocked_ord<2>(T, v, ctl, sc, s);
+    switch (ord) {
+      case 1: return launch_blocked_ord<1>(T, v, ctl, sc, s, bs);
+      case 2: return launch_blocked_ord<2>(T, v, ctl, sc, s, bs);
+      case 3: return launch_blocked_ord<3>(T, v, ctl, sc, s, bs);
+    }
+    return hipErrorInvalidValue;
   }
   switch (prec) {
     case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s);

@@ -85,6 +85,12 @@ struct GridView {
   double omega;
 };
 
+// Block shape of a block-parallel pass, in interior cells (>= 1 each).
+struct BlockShape {
+  int32_t rows = 1;
+  int32_t cols = 1;
+};
+
 // ---------------------------------------------------------------------------
 // Batched solves: many grids advanced by one persistent kernel.
 //
@@ -268,13 +274,15 @@ hipError_t launch_unpack(int prec, const void *grid, void *u, int64_t pitch,
 hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
 // Blocked pass of T iterations from v.in into v.out: red-black (ord 0, T in
-// 1..kTMax, every precision), four-colour (ord 1, T in 1..kTMaxC4, FP64) or
-// Jacobi (ord 2, T in 1..kTMax, FP64); the view's nstrips/nseg must match T
-// and the ordering.  ctl == nullptr runs without maxima, verdict or early
+// 1..kTMax, every precision), four-colour (ord 1, T in 1..kTMaxC4, FP64),
+// Jacobi (ord 2, T in 1..kTMax, FP64) or block-parallel red-black (ord 3, T
+// in 1..kTMax, FP64, blocks of shape bs); the view's nstrips/nseg must match
+// T and the ordering.  ctl == nullptr runs without maxima, verdict or early
 // exit.
 constexpr int kTMaxC4 = 5;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
-                               const Sched &sc, hipStream_t s, int ord = 0);
+                               const Sched &sc, hipStream_t s, int ord = 0,
+                               const BlockShape &bs = BlockShape{});
 bool blocked_T_supported(int T);
 bool blocked_ord_T_supported(int ord, int T);
 // Pass-kernel workgroups (wavefronts) resident per CU; 0 if the query fails.

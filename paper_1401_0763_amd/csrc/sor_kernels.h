@@ -229,16 +229,16 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
   }
 }
 
-// Stage pipelines of the blocked tile by ordering: red-black (0) applies 2
-// half-sweeps per iteration; the four-colour ordering (1) 3 (colour 0,
-// colours 1 and 2, colour 3); Jacobi (2) one sweep of every cell from the
-// previous iterate.  The row halo is the stage count rounded up to even, so
+// Stage pipelines of the blocked tile by ordering: red-black (0) and
+// block-parallel red-black (3) apply 2 half-sweeps per iteration; the
+// four-colour ordering (1) 3 (colour 0, colours 1 and 2, colour 3); Jacobi
+// (2) one sweep of every cell from the previous iterate.  The row halo is the stage count rounded up to even, so
 // a tile's first loaded row keeps the parity of its first core row.  The
 // register window holds the stage rows, their neighbours and the
 // SOR_PREFETCH rows loaded ahead, rounded up to even; the row walk runs in
 // chunks of that many steps.
 __host__ __device__ constexpr int order_stages(int ord, int T) {
-  return (ord == 0 ? 2 : ord == 1 ? 3 : 1) * T;
+  return (ord == 0 || ord == 3 ? 2 : ord == 1 ? 3 : 1) * T;
 }
 __host__ __device__ constexpr int order_row_halo(int ord, int T) {
   return (order_stages(ord, T) + 1) / 2 * 2;
@@ -277,7 +277,14 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 //
 // The other orderings (ORD, FP64 only) run the same walk, window, halo and
 // stores with their own stage lists; they are described where they branch
-// off below.
+// off below.  The block-parallel ordering (3) is the red-black pipeline in
+// which a black cell takes a red neighbour that lies in another block (of
+// bs.rows x bs.cols interior cells) at its value before this
+// iteration's red half-sweep: each red stage keeps the values it overwrites
+// for the two steps in which the next stage can still need them, and sends
+// the old edge value across lanes beside the new one.  The dependency cone
+// is the red-black one (a black cell's update reaches two cells back into
+// the previous iterate), so the halo is unchanged.
 //
 // One branch-free body serves every tile.  Boundary and out-of-grid cells
 // must keep their value; they get a relaxation factor of 0 instead of omega
@@ -305,12 +312,14 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0, bool DYN = false>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
-                                             bool &bad, int s_run = 2 * T) {
+                                             bool &bad, int s_run = 2 * T,
+                                             const BlockShape bs = BlockShape{}) {
   using st = typename PT<P>::st;
   using ct = typename PT<P>::ct;
   constexpr int V = PT<P>::V;
   static_assert(ORD == 0 || P == kF64, "other orderings are instantiated for FP64");
   static_assert(!DYN || ORD == 0, "a run-time depth is implemented for red-black passes");
+  static_assert(ORD != 3 || PT<P>::V == 2, "block-parallel passes hold one red cell per lane");
   constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
   constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
@@ -362,6 +371,23 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 #pragma unroll
   for (int v = 0; v < V; ++v) fmask[v] = (lane_store && omc[v] != (ct)0) ? 0x7fffffffu : 0u;
   unsigned fhi = 0;
+  // Block-parallel: per cell of this lane, whether its west (bx_w) or east
+  // (bx_e) neighbour lies in another block; per window slot (bit), whether
+  // the row's north (rx_n) or south (rx_s) neighbour does.  Cells and rows
+  // off the interior never change, so their flags do not matter.
+  constexpr bool BP = ORD == 3;
+  bool bx_w[V], bx_e[V];
+  unsigned rx_n = 0, rx_s = 0;
+  int rib = 0;                                   // (row - 1) mod blk_rows of the next load
+  if constexpr (BP) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int c = col0 + v;
+      bx_w[v] = c >= 2 && c <= n && (c - 1) % bs.cols == 0;
+      bx_e[v] = c >= 1 && c < n && c % bs.cols == 0;
+    }
+    rib = ((a - 1) % bs.rows + bs.rows) % bs.rows;
+  }
 
   ct w[W][V];                                    // row window
   ct fw[POIS ? W : 1][V];                        // h*h*f of the window rows
@@ -385,6 +411,12 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     constexpr int sp = decltype(SP)::value;
     wc[sp] = (rn >= rlo && rn < rhi) ? (ct)1 : (ct)0;
     wr[sp] = (rn >= 1 && rn <= n) ? (ct)1 : (ct)0;
+    if constexpr (BP) {
+      const unsigned bit = 1u << sp;
+      rx_n = (rn >= 2 && rn <= n && rib == 0) ? (rx_n | bit) : (rx_n & ~bit);
+      rx_s = (rn >= 1 && rn < n && rib == bs.rows - 1) ? (rx_s | bit) : (rx_s & ~bit);
+      rib = rib + 1 == bs.rows ? 0 : rib + 1;
+    }
     const unsigned soff = (unsigned)(min(rn, b - 1) - a) * rowbytes;
     const Vec<P> x = buf_load<P, COH>(rin, lane_off, soff);
 #pragma unroll
@@ -407,7 +439,16 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   ct xs[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
-  if constexpr (ORD == 0) xs[0] = lane_permute(from_hi, w[1][0]);
+  if constexpr (ORD == 0 || BP) xs[0] = lane_permute(from_hi, w[1][0]);
+  // Block-parallel: the red values that red stage t overwrote this step
+  // (ob0), one step earlier (ob1) and two steps earlier (ob2), and the old
+  // edge value received from the adjacent lane (xo, sent one step earlier).
+  constexpr int TB = BP ? T : 1;
+  ct ob0[TB], ob1[TB], ob2[TB], xo[TB], xon[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    ob0[t] = ob1[t] = ob2[t] = xo[t] = xon[t] = (ct)0;
+  }
   // Jacobi: every stage needs both cross-lane neighbours (xs from the lane
   // below, xr from the lane above) and the row above its row at its own
   // input level (pv), which the stage itself overwrote one step earlier.
@@ -446,10 +487,17 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       constexpr int ve = v0 == 1 ? V - 1 : 0;
       const int to = v0 == 1 ? from_lo : from_hi;
       ct xn[S];
-      if constexpr (ORD == 0) {
+      if constexpr (ORD == 0 || BP) {
       // Stage 0 of the next step updates row r+1, still at level 0 here; its
       // exchange goes first, since it is the first one used.
       xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
+      if constexpr (BP) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          ob2[t] = ob1[t];
+          ob1[t] = ob0[t];
+        }
+      }
       // Stage k (half-sweep k) on row r-k.
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
@@ -460,9 +508,25 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
           constexpr int v = v0 + 2 * decltype(JV)::value;
           const ct self = w[sq][v];
-          const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
-          const ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
-          ct s = (w[su][v] + w[sd][v]) + (left + right);
+          ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
+          ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
+          ct up = w[su][v], down = w[sd][v];
+          if constexpr (BP && (k & 1)) {
+            // Black half-sweep of iteration k/2: a red neighbour in another
+            // block at its value before this iteration's red half-sweep (row
+            // above: kept two steps ago, row below: this step, same row: one
+            // step ago in this lane or sent from the adjacent one).
+            constexpr int t = k >> 1;
+            if ((rx_n >> sq) & 1u) up = ob2[t];
+            if ((rx_s >> sq) & 1u) down = ob0[t];
+            if (bx_w[v]) left = v == 0 ? xo[t] : ob1[t];
+            if (bx_e[v]) right = v == V - 1 ? xo[t] : ob1[t];
+          }
+          if constexpr (BP && !(k & 1)) {
+            ob0[k >> 1] = self;
+            if constexpr (v == ve) xon[k >> 1] = lane_permute(to, self);
+          }
+          ct s = (up + down) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
           const ct dg = vfma((ct)0.25, s, -self);      // Gauss-Seidel value - self
           // Eq. 1 with one rounding; with binary16 storage the step is rounded
@@ -578,6 +642,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) xs[k] = xn[k];
+      if constexpr (BP) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) xo[t] = xon[t];
+      }
       // Row r-S+1 has had all S half-sweeps: store it if it is a core row.
       constexpr int so = ((i + 2 - S) % W + W) % W;
       const int qo = r - S + 1;
@@ -605,13 +673,14 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 // earlier pass met the stopping rule, then reports its maxima.
 template <int P, int T, bool POIS, int ORD>
 __device__ __forceinline__ void blocked_pass_body(const GridView &g, Ctl *ctl,
-                                                  const Sched &sc) {
+                                                  const Sched &sc,
+                                                  const BlockShape bs = BlockShape{}) {
   if (ctl && ctl_stopped(ctl)) return;
   using ct = typename PT<P>::ct;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   ct m[T];
   bool bad = false;
-  blocked_tile<P, T, POIS, kCohDefault, ORD>(g, tile, m, bad);
+  blocked_tile<P, T, POIS, kCohDefault, ORD>(g, tile, m, bad, 2 * T, bs);
   if (!ctl) return;
   double mx[T];
 #pragma unroll
@@ -638,6 +707,13 @@ template <int P, int T, bool POIS>
 __global__ __launch_bounds__(64) void blocked_pass_jacobi_kernel(GridView g, Ctl *ctl,
                                                                  Sched sc) {
   blocked_pass_body<P, T, POIS, 2>(g, ctl, sc);
+}
+
+// Block-parallel passes (blocks of bs).
+template <int P, int T, bool POIS>
+__global__ __launch_bounds__(64) void blocked_pass_bp_kernel(GridView g, Ctl *ctl,
+                                                             Sched sc, BlockShape bs) {
+  blocked_pass_body<P, T, POIS, 3>(g, ctl, sc, bs);
 }
 
 // Device-scope scalar loads and stores (relaxed agent-scope atomics, i.e.
@@ -757,18 +833,28 @@ template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 1> {
 template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 2> {
   static constexpr auto k = blocked_pass_jacobi_kernel<P, T, POIS>;
 };
+template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 3> {
+  static constexpr auto k = blocked_pass_bp_kernel<P, T, POIS>;
+};
 
 // Host-side launch of the blocked pass for one (precision, T); each pair is
 // instantiated in its own translation unit so the unrolled bodies compile in
 // parallel.
 template <int P, int T, int ORD = 0>
 hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
-                             hipStream_t s) {
+                             hipStream_t s, const BlockShape &bs = BlockShape{}) {
   const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
-  if (v.F)
-    hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
-  else
-    hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
+  if constexpr (ORD == 3) {
+    if (v.F)
+      hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc, bs);
+    else
+      hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc, bs);
+  } else {
+    if (v.F)
+      hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
+    else
+      hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
+  }
   return hipGetLastError();
 }
 

@@ -59,6 +59,8 @@ def test_newer_entry_points_reject_a_null_context():
                                None, None) == sor.EINVAL
     assert lib.sor_solve_variant_f64(None, 1, None, None, None, 8, 1.0, 1e-6, 10, 1,
                                      None, None, None) == sor.EINVAL
+    assert lib.sor_solve_blockpar_f64(None, None, None, None, 8, 1.0, 4, 4, 1e-6, 10, 1,
+                                      None, None, None) == sor.EINVAL
     assert lib.sor_ctx_set_tiling3d(None, 0, 0, 0, 0) == sor.EINVAL
     tl = sor._Tiling(4, 64)
     assert lib.sor_ctx_set_variant_tiling(None, sor.ORDER_FOUR_COLOUR,
