@@ -33,8 +33,9 @@ Under "forms" the same line reports:
   control_8192  8192^2, 300 iterations: grids beyond the Infinity Cache;
   3d       the 3-D extension (7-point stencil), 256^3, 1000 iterations and
            to 1e-8, with the CPU oracle timed on 200 iterations;
-  variants the Jacobi and four-colour orderings on 4096^2 (200 iterations)
-           and iterations to 1e-8 on 128^2 beside red-black;
+  variants the Jacobi and four-colour orderings and block-parallel SOR
+           (128 x 128 blocks) on 4096^2 (200 iterations) and iterations to
+           1e-8 on 128^2 beside red-black;
 and, each against plain one-grid-at-a-time FP64 on the same GPU:
   mixed    4096^2 Poisson (f = N(0,1) + 2 pi^2 sin sin, seed 3): FP64 defect
            correction around FP32 inner sweeps vs plain FP64 SOR, each run to
