@@ -173,13 +173,13 @@ int pass_ordering(int32_t ordering) {
 // Tiling of a four-colour or Jacobi solve (pass ordering ord): the context's
 // setting, with seg_rows from auto_seg_rows when none was set.
 sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
-  sor_tiling t = c->tiling_var[ord];
+  sor_tiling t = c->tiling_var[ord == 4 ? 3 : ord];      // both block-parallel kernels
   if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, kF64, n, t.iters_per_pass, pois, ord);
   return t;
 }
 
 // Run SOR sweeps (red-black; four-colour with ord 1, Jacobi with ord 2 or
-// block-parallel red-black with ord 3 and blocks of shape bs on
+// block-parallel red-black with ord 3 or 4 and blocks of shape bs on
 // FP64 grids, where the simple kernel is the in-place four-colour one) on the
 // packed grids A/B (same layout L) until the stopping rule or max_iters.  On
 // return *result_grid is the grid holding the final iterate.  hist (host, may
@@ -193,7 +193,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   const sor_tiling tl = ord ? variant_tiling(c, ord, L.n, F != nullptr)
                             : tuned_tiling(c, prec, L.n, F != nullptr);
   // Jacobi and block-parallel passes read the previous iterate: ping-pong only.
-  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2 && ord != 3;
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2 && ord < 3;
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 
@@ -718,8 +718,12 @@ sor_status solve_ordered(sor_ctx *c, int32_t ordering, double *u, const double *
     });
     res_grid = (out->passes & 1) ? B : A;
   } else {
-    st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid,
-                    pass_ordering(ordering), ctl, BlockShape{blk_rows, blk_cols});
+    int ord = pass_ordering(ordering);
+    // Block-parallel with blocks of even width (or no column edge inside the
+    // grid): the kernel without cross-lane old values.
+    if (ord == 3 && (blk_cols % 2 == 0 || blk_cols >= n)) ord = 4;
+    st = run_sweeps(c, kF64, L, A, B, F, omega, sc, s, out, hist, &res_grid, ord, ctl,
+                    BlockShape{blk_rows, blk_cols});
   }
   if (st == SOR_OK || st == SOR_NOT_CONVERGED || st == SOR_ENONFINITE) {
     HIP_TRY(c, launch_unpack(kF64, res_grid, u, L.pitch, n, s));

@@ -365,6 +365,10 @@ SOR_EXTERN_BLOCKED_ORD(1, 3) SOR_EXTERN_BLOCKED_ORD(2, 3)
 SOR_EXTERN_BLOCKED_ORD(3, 3) SOR_EXTERN_BLOCKED_ORD(4, 3)
 SOR_EXTERN_BLOCKED_ORD(5, 3) SOR_EXTERN_BLOCKED_ORD(6, 3)
 SOR_EXTERN_BLOCKED_ORD(7, 3) SOR_EXTERN_BLOCKED_ORD(8, 3)
+SOR_EXTERN_BLOCKED_ORD(1, 4) SOR_EXTERN_BLOCKED_ORD(2, 4)
+SOR_EXTERN_BLOCKED_ORD(3, 4) SOR_EXTERN_BLOCKED_ORD(4, 4)
+SOR_EXTERN_BLOCKED_ORD(5, 4) SOR_EXTERN_BLOCKED_ORD(6, 4)
+SOR_EXTERN_BLOCKED_ORD(7, 4) SOR_EXTERN_BLOCKED_ORD(8, 4)
 
 // Passes of the other orderings (FP64 only).
 template <int ORD>
@@ -379,7 +383,7 @@ static hipError_t launch_blocked_ord(int T, const GridView &v, Ctl *ctl, const S
   if constexpr (ORD == 1) {
     if (T == 5) return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s, bs);
   }
-  if constexpr (ORD == 2 || ORD == 3) {
+  if constexpr (ORD >= 2) {
     switch (T) {
       case 5: return launch_blocked_PT<kF64, 5, ORD>(v, ctl, sc, s, bs);
       case 6: return launch_blocked_PT<kF64, 6, ORD>(v, ctl, sc, s, bs);
@@ -401,7 +405,7 @@ static int blocked_blocks_per_cu_ord(int T, bool pois) {
   if constexpr (ORD == 1) {
     if (T == 5) return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
   }
-  if constexpr (ORD == 2 || ORD == 3) {
+  if constexpr (ORD >= 2) {
     switch (T) {
       case 5: return blocked_blocks_per_cu<kF64, 5, ORD>(pois);
       case 6: return blocked_blocks_per_cu<kF64, 6, ORD>(pois);
@@ -450,6 +454,7 @@ int blocked_blocks_per_cu(int prec, int T, bool pois, int ord) {
       case 1: return blocked_blocks_per_cu_ord<1>(T, pois);
       case 2: return blocked_blocks_per_cu_ord<2>(T, pois);
       case 3: return blocked_blocks_per_cu_ord<3>(T, pois);
+      case 4: return blocked_blocks_per_cu_ord<4>(T, pois);
     }
     return 0;
   }
@@ -478,6 +483,7 @@ hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
       case 1: return launch_blocked_ord<1>(T, v, ctl, sc, s, bs);
       case 2: return launch_blocked_ord<2>(T, v, ctl, sc, s, bs);
       case 3: return launch_blocked_ord<3>(T, v, ctl, sc, s, bs);
+      case 4: return launch_blocked_ord<4>(T, v, ctl, sc, s, bs);
     }
     return hipErrorInvalidValue;
   }

@@ -49,7 +49,8 @@ struct sor_ctx {
   // Blocked passes of the other orderings, by pass ordering (1 four-colour,
   // 2 Jacobi, 3 block-parallel; 0 unused); seg 0: by size.
   sor_tiling tiling_var[4] = {{0, 0}, {5, 0}, {8, 0}, {5, 0}};
-  int occ_var[4][sor::kTMax + 1][2] = {};              // their pass blocks per CU (lazy)
+  int occ_var[5][sor::kTMax + 1][2] = {};              // their pass blocks per CU (lazy;
+                                                       // 4: block-parallel, even width)
   int tiling3d[4] = {0, 0, 0, 0};                      // 3-D T, cx, cy, zs; 0: auto
   int occ3[2][2] = {};                                 // 3-D stream blocks per CU (lazy)
   void *scratch = nullptr;                             // allocation-free solve's memory

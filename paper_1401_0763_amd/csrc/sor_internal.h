@@ -275,9 +275,9 @@ hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
                             hipStream_t s);
 // Blocked pass of T iterations from v.in into v.out: red-black (ord 0, T in
 // 1..kTMax, every precision), four-colour (ord 1, T in 1..kTMaxC4, FP64),
-// Jacobi (ord 2, T in 1..kTMax, FP64) or block-parallel red-black (ord 3, T
-// in 1..kTMax, FP64, blocks of shape bs); the view's nstrips/nseg must match
-// T and the ordering.  ctl == nullptr runs without maxima, verdict or early
+// Jacobi (ord 2, T in 1..kTMax, FP64) or block-parallel red-black (ord 3, or
+// 4 when bs.cols is even or at least n; T in 1..kTMax, FP64, blocks of shape
+// bs); the view's nstrips/nseg must match T and the ordering.  ctl == nullptr runs without maxima, verdict or early
 // exit.
 constexpr int kTMaxC4 = 5;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,

@@ -230,7 +230,8 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 }
 
 // Stage pipelines of the blocked tile by ordering: red-black (0) and
-// block-parallel red-black (3) apply 2 half-sweeps per iteration; the
+// block-parallel red-black (3; 4 for blocks of even width) apply 2
+// half-sweeps per iteration; the
 // four-colour ordering (1) 3 (colour 0, colours 1 and 2, colour 3); Jacobi
 // (2) one sweep of every cell from the previous iterate.  The row halo is the stage count rounded up to even, so
 // a tile's first loaded row keeps the parity of its first core row.  The
@@ -238,7 +239,7 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 // SOR_PREFETCH rows loaded ahead, rounded up to even; the row walk runs in
 // chunks of that many steps.
 __host__ __device__ constexpr int order_stages(int ord, int T) {
-  return (ord == 0 || ord == 3 ? 2 : ord == 1 ? 3 : 1) * T;
+  return (ord == 0 || ord >= 3 ? 2 : ord == 1 ? 3 : 1) * T;
 }
 __host__ __device__ constexpr int order_row_halo(int ord, int T) {
   return (order_stages(ord, T) + 1) / 2 * 2;
@@ -284,7 +285,10 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // for the two steps in which the next stage can still need them, and sends
 // the old edge value across lanes beside the new one.  The dependency cone
 // is the red-black one (a black cell's update reaches two cells back into
-// the previous iterate), so the halo is unchanged.
+// the previous iterate), so the halo is unchanged.  With blocks of even
+// width (ordering 4) every column edge falls between the two cells of one
+// lane (blocks start at odd columns, lanes at even ones), so no old value
+// crosses lanes and one flag per lane says whether its pair is split.
 //
 // One branch-free body serves every tile.  Boundary and out-of-grid cells
 // must keep their value; they get a relaxation factor of 0 instead of omega
@@ -319,7 +323,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   constexpr int V = PT<P>::V;
   static_assert(ORD == 0 || P == kF64, "other orderings are instantiated for FP64");
   static_assert(!DYN || ORD == 0, "a run-time depth is implemented for red-black passes");
-  static_assert(ORD != 3 || PT<P>::V == 2, "block-parallel passes hold one red cell per lane");
+  static_assert(ORD < 3 || PT<P>::V == 2, "block-parallel passes hold one red cell per lane");
   constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
   constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
@@ -375,8 +379,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   // (bx_e) neighbour lies in another block; per window slot (bit), whether
   // the row's north (rx_n) or south (rx_s) neighbour does.  Cells and rows
   // off the interior never change, so their flags do not matter.
-  constexpr bool BP = ORD == 3;
+  constexpr bool BP = ORD == 3 || ORD == 4;
+  constexpr bool BPE = ORD == 4;                 // even block width
   bool bx_w[V], bx_e[V];
+  bool bx_in = false;                            // BPE: a block edge splits this lane's pair
   unsigned rx_n = 0, rx_s = 0;
   int rib = 0;                                   // (row - 1) mod blk_rows of the next load
   if constexpr (BP) {
@@ -386,6 +392,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       bx_w[v] = c >= 2 && c <= n && (c - 1) % bs.cols == 0;
       bx_e[v] = c >= 1 && c < n && c % bs.cols == 0;
     }
+    bx_in = bx_e[0];
     rib = ((a - 1) % bs.rows + bs.rows) % bs.rows;
   }
 
@@ -440,6 +447,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
   if constexpr (ORD == 0 || BP) xs[0] = lane_permute(from_hi, w[1][0]);
+  static_assert(!BPE || V == 2, "an even block width splits a lane pair at most once");
   // Block-parallel: the red values that red stage t overwrote this step
   // (ob0), one step earlier (ob1) and two steps earlier (ob2), and the old
   // edge value received from the adjacent lane (xo, sent one step earlier).
@@ -519,12 +527,19 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
             constexpr int t = k >> 1;
             if ((rx_n >> sq) & 1u) up = ob2[t];
             if ((rx_s >> sq) & 1u) down = ob0[t];
-            if (bx_w[v]) left = v == 0 ? xo[t] : ob1[t];
-            if (bx_e[v]) right = v == V - 1 ? xo[t] : ob1[t];
+            if constexpr (BPE) {
+              if (bx_in) {
+                if constexpr (v == 0) right = ob1[t];
+                else left = ob1[t];
+              }
+            } else {
+              if (bx_w[v]) left = v == 0 ? xo[t] : ob1[t];
+              if (bx_e[v]) right = v == V - 1 ? xo[t] : ob1[t];
+            }
           }
           if constexpr (BP && !(k & 1)) {
             ob0[k >> 1] = self;
-            if constexpr (v == ve) xon[k >> 1] = lane_permute(to, self);
+            if constexpr (v == ve && !BPE) xon[k >> 1] = lane_permute(to, self);
           }
           ct s = (up + down) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
@@ -642,7 +657,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) xs[k] = xn[k];
-      if constexpr (BP) {
+      if constexpr (BP && !BPE) {
 #pragma unroll
         for (int t = 0; t < T; ++t) xo[t] = xon[t];
       }
@@ -709,11 +724,16 @@ __global__ __launch_bounds__(64) void blocked_pass_jacobi_kernel(GridView g, Ctl
   blocked_pass_body<P, T, POIS, 2>(g, ctl, sc);
 }
 
-// Block-parallel passes (blocks of bs).
+// Block-parallel passes (blocks of bs; of even width: the _even kernel).
 template <int P, int T, bool POIS>
 __global__ __launch_bounds__(64) void blocked_pass_bp_kernel(GridView g, Ctl *ctl,
                                                              Sched sc, BlockShape bs) {
   blocked_pass_body<P, T, POIS, 3>(g, ctl, sc, bs);
+}
+template <int P, int T, bool POIS>
+__global__ __launch_bounds__(64) void blocked_pass_bp_even_kernel(GridView g, Ctl *ctl,
+                                                                  Sched sc, BlockShape bs) {
+  blocked_pass_body<P, T, POIS, 4>(g, ctl, sc, bs);
 }
 
 // Device-scope scalar loads and stores (relaxed agent-scope atomics, i.e.
@@ -836,6 +856,9 @@ template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 2> {
 template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 3> {
   static constexpr auto k = blocked_pass_bp_kernel<P, T, POIS>;
 };
+template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 4> {
+  static constexpr auto k = blocked_pass_bp_even_kernel<P, T, POIS>;
+};
 
 // Host-side launch of the blocked pass for one (precision, T); each pair is
 // instantiated in its own translation unit so the unrolled bodies compile in
@@ -844,7 +867,7 @@ template <int P, int T, int ORD = 0>
 hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
                              hipStream_t s, const BlockShape &bs = BlockShape{}) {
   const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
-  if constexpr (ORD == 3) {
+  if constexpr (ORD >= 3) {
     if (v.F)
       hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc, bs);
     else

@@ -3,7 +3,9 @@ Mittal 2014 names; blocks updated together, red-black inside a block, a
 neighbour in another block at the previous iterate) against the oracle on
 identical seeded inputs: final grid, every iteration's largest change and the
 stop iteration agree bit for bit, for every pass depth, tilings whose tiles
-cut blocks anywhere, ragged blocks and grids, and the two limits."""
+cut blocks anywhere, ragged blocks and grids, and the two limits.  Blocks of
+even width (or wider than the grid) run a kernel of their own, so the cases
+mix even and odd widths."""
 import sys
 
 import numpy as np
@@ -118,15 +120,17 @@ def test_to_tolerance_same_stop(sor, ctx, K):
 
 @pytest.mark.parametrize("T", [2, 3, 5, 8])
 @pytest.mark.parametrize("K", [1, 3, 7])
-def test_stop_inside_a_pass(sor, ctx, T, K):
+@pytest.mark.parametrize("bc", [11, 10])
+def test_stop_inside_a_pass(sor, ctx, T, K, bc):
     """Checks that fall inside a pass: the pass is redone up to the stop from
-    its input grid, so the result is the stopping iteration's."""
+    its input grid, so the result is the stopping iteration's (blocks of odd
+    and of even width, which run different kernels)."""
     n = 70
     g = random_small(77 + T, n, with_f=False)
     ctx.set_variant_tiling(sor.ORDER_BLOCK_PARALLEL, T, 0)
-    ref = oracle.blockpar_f64(g.u0, g.bdy, None, 1.1, 9, 11, 1e-4, 100000, K, hist=True)
+    ref = oracle.blockpar_f64(g.u0, g.bdy, None, 1.1, 9, bc, 1e-4, 100000, K, hist=True)
     assert ref.status == oracle.OK
-    res, u = run(sor, ctx, g, 9, 11, 1.1, 1e-4, 100000, K)
+    res, u = run(sor, ctx, g, 9, bc, 1.1, 1e-4, 100000, K)
     assert (res.status, res.iterations) == (sor.OK, ref.iterations)
     assert res.final_max_delta == ref.final_max_delta
     assert_bitwise(u, ref.u, f"u T={T} K={K}")
@@ -208,3 +212,87 @@ def test_argument_errors(sor, ctx):
     u = dev(g.u0)
     r = sor.solve_blockpar_f64(u, dev(bdy), 4, 4, None, 1.0, 1e-6, 50, 1, ctx=ctx)
     assert r.status == sor.ENONFINITE
+
+
+@pytest.mark.parametrize("n", [1, 130])
+def test_nan_from_finite_operands_reported(sor, ctx, n):
+    """A NaN made from finite operands ((+inf) + (-inf) in a neighbour sum),
+    whose change the running maximum drops: ENONFINITE like the oracle, at
+    every depth (the passes check every interior cell they store)."""
+    from test_nonfinite_gpu import interior_cross, opposite_boundary
+    g = opposite_boundary(1, 64) if n == 1 else interior_cross(n, 64)
+    for br, bc in ((1, 1), (4, 6), (n, n)):
+        ref = oracle.blockpar_f64(g.u0, g.bdy, None, 1.0, br, bc, 0.0, 30, 10, hist=True)
+        assert ref.status == oracle.ENONFINITE and ref.iterations == 1
+        for T in (1, 3, 5, 8):
+            ctx.set_variant_tiling(sor.ORDER_BLOCK_PARALLEL, T, 0)
+            _say(f"blockpar nan-from-finite n={n} blocks {br}x{bc} T={T}")
+            res, _ = run(sor, ctx, Grid(n, g.u0, g.bdy, None, 1.0), br, bc, 1.0, 0.0, 30, 10)
+            assert res.status == sor.ENONFINITE and not res.converged, (T, res)
+            assert 1 <= res.iterations <= T, (T, res.iterations)
+
+
+def test_largest_side_sampled_windows(sor):
+    """n = 65536 (two 34 GB working grids), 7 x 7 blocks, 2 iterations.  An
+    iteration moves information by at most two cells (a black cell reads red
+    values that read black ones), so the oracle on a window whose ring is
+    frozen at the initial values is exact more than 2k cells inside it; the
+    windows start at multiples of 7 with an even sum of offsets, so they see
+    the same blocks and colours as the whole grid (65513 = 7 x 9359 puts the
+    last windows against the south and east edges)."""
+    n, k, blk = 65536, 2, 7
+    rw = 12
+    m = 2 * rw - 1
+    core = slice(2 * k + 1, m - (2 * k + 1))
+    ctx = sor.Context(0)
+    try:
+        rng = np.random.default_rng(65539)
+        bdy = rng.uniform(0.0, 100.0, size=4 * n)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(23)
+        _say("blockpar n=65536: filling u0 on the device")
+        u = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=gen) * 100.0
+        last = n + 1 - 2 * rw                      # 65513, a multiple of 7, odd
+        corners = [(0, 0), (0, 65506), (last, last), (65506, 0), (32760, 32774),
+                   (1001, 7), (14, 31010), (40005, 7)]
+        for a, b in corners:
+            assert a % blk == 0 and b % blk == 0 and (a + b) % 2 == 0 and a <= last and b <= last
+        before = {}
+        for a, b in corners:
+            lo_i, lo_j = max(a - 1, 0), max(b - 1, 0)
+            before[(a, b)] = u[lo_i:a + 2 * rw, lo_j:b + 2 * rw].cpu().numpy().copy()
+        _say("blockpar n=65536: solving")
+        res = sor.solve_blockpar_f64(u, torch.tensor(bdy, dtype=torch.float64, device="cuda"),
+                                     blk, blk, None, 1.3, 0.0, k, 1, hist=False, ctx=ctx)
+        assert res.status == sor.NOT_CONVERGED and res.iterations == k
+
+        def val_fn(blk_arr, lo_i, lo_j):
+            def val(i, j):
+                if i == 0:
+                    return bdy[j - 1]
+                if i == n + 1:
+                    return bdy[n + j - 1]
+                if j == 0:
+                    return bdy[2 * n + i - 1]
+                if j == n + 1:
+                    return bdy[3 * n + i - 1]
+                return blk_arr[i - 1 - lo_i, j - 1 - lo_j]
+            return val
+
+        for a, b in corners:
+            _say(f"blockpar window at ({a}, {b})")
+            lo_i, lo_j = max(a - 1, 0), max(b - 1, 0)
+            val = val_fn(before[(a, b)], lo_i, lo_j)
+            w0 = np.array([[val(a + 1 + r, b + 1 + c) for c in range(m)] for r in range(m)])
+            wb = np.concatenate([[val(a, b + 1 + c) for c in range(m)],
+                                 [val(a + 2 * rw, b + 1 + c) for c in range(m)],
+                                 [val(a + 1 + r, b) for r in range(m)],
+                                 [val(a + 1 + r, b + 2 * rw) for r in range(m)]])
+            ref = oracle.blockpar_f64(w0, wb, None, 1.3, blk, blk, 0.0, k, 1)
+            got = u[a:a + m, b:b + m].cpu().numpy()
+            assert np.array_equal(got[core, core].view(np.uint64),
+                                  ref.u[core, core].view(np.uint64)), (a, b)
+        del u
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
