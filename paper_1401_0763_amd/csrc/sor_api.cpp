@@ -170,8 +170,9 @@ int pass_ordering(int32_t ordering) {
   return -1;
 }
 
-// Tiling of a four-colour or Jacobi solve (pass ordering ord): the context's
-// setting, with seg_rows from auto_seg_rows when none was set.
+// Tiling of a four-colour, Jacobi or block-parallel solve (pass ordering
+// ord): the context's setting, with seg_rows from auto_seg_rows when none
+// was set.
 sor_tiling variant_tiling(sor_ctx *c, int ord, int n, bool pois) {
   sor_tiling t = c->tiling_var[ord == 4 ? 3 : ord];      // both block-parallel kernels
   if (t.seg_rows == 0) t.seg_rows = auto_seg_rows(c, kF64, n, t.iters_per_pass, pois, ord);
@@ -193,7 +194,7 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
   const sor_tiling tl = ord ? variant_tiling(c, ord, L.n, F != nullptr)
                             : tuned_tiling(c, prec, L.n, F != nullptr);
   // Jacobi and block-parallel passes read the previous iterate: ping-pong only.
-  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord != 2 && ord < 3;
+  const bool simple = c->kernel == SOR_KERNEL_SIMPLE && ord <= 1;
   const int T = simple ? 1 : tl.iters_per_pass;
   GridView base = make_view(L, prec, tl, A, B, F, omega, ord);
 

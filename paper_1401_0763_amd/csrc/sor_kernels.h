@@ -231,9 +231,9 @@ __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_
 
 // Stage pipelines of the blocked tile by ordering: red-black (0) and
 // block-parallel red-black (3; 4 for blocks of even width) apply 2
-// half-sweeps per iteration; the
-// four-colour ordering (1) 3 (colour 0, colours 1 and 2, colour 3); Jacobi
-// (2) one sweep of every cell from the previous iterate.  The row halo is the stage count rounded up to even, so
+// half-sweeps per iteration; the four-colour ordering (1) 3 (colour 0,
+// colours 1 and 2, colour 3); Jacobi (2) one sweep of every cell from the
+// previous iterate.  The row halo is the stage count rounded up to even, so
 // a tile's first loaded row keeps the parity of its first core row.  The
 // register window holds the stage rows, their neighbours and the
 // SOR_PREFETCH rows loaded ahead, rounded up to even; the row walk runs in
@@ -447,7 +447,6 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
   if constexpr (ORD == 0 || BP) xs[0] = lane_permute(from_hi, w[1][0]);
-  static_assert(!BPE || V == 2, "an even block width splits a lane pair at most once");
   // Block-parallel: the red values that red stage t overwrote this step
   // (ob0), one step earlier (ob1) and two steps earlier (ob2), and the old
   // edge value received from the adjacent lane (xo, sent one step earlier).
