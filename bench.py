@@ -717,9 +717,9 @@ def main():
                          "many MiB (a known-size reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a grid would shard into row slabs with 2T-row ghost zones exchanged "
+              "once per pass); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
