@@ -118,12 +118,14 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * A new context reports both as 0 (chosen per solve).  Until iters_per_pass
  * is set, each plain solve uses 7 where the 7-deep pass kernel keeps two
  * wavefronts resident per SIMD for the solve's precision and problem (FP64
- * and FP32 Laplace problems on gfx950), else 6; batched solves use the largest of 4,
- * 2 and 1 not above the context's depth (6 while it is automatic).  Until
- * seg_rows is set, each plain solve picks it from the grid side, so that a
- * pass has about as many tiles as the device holds resident wavefronts of the
- * pass kernel (2*2*iters_per_pass..768 rows); batched solves use 64 rows
- * below n = 512, else 192 (FP64) or 96.  An
+ * and FP32 Laplace problems on gfx950), else 6; batched FP64 solves always
+ * run passes of 6 iterations (shorter ones only to finish a solve), and the
+ * inner sweeps of batched and served mixed solves use the context's depth
+ * capped at 4.  Until seg_rows is set, each plain solve picks it from the
+ * grid side, so that a pass has about as many tiles as the device holds
+ * resident wavefronts of the pass kernel (2*2*iters_per_pass..768 rows);
+ * batched FP64 solves use 128 rows below n = 512, else 384, and mixed inner
+ * sweeps 64 rows below n = 512, else 96.  An
  * autotuned entry for the grid's size class (sor_autotune for plain solves,
  * sor_autotune_batch for batched ones) takes precedence.  Results do not
  * depend on the tiling. */
@@ -467,9 +469,10 @@ sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best)
  * Tiling autotuner for grids inside batched launches, where many grids share
  * the chip and throughput, not one grid's pass latency, decides: solves a
  * scratch batch of identical n x n grids (enough for about 4096 tiles, at
- * most 256 grids and 1 GiB; 96 iterations each) once per candidate (1, 2 or
- * 4 iterations per pass x 16..384 rows) with sor_batch_solve_f64 (bits 64)
- * or the inner sweeps of sor_batch_solve_mixed (bits 32 or 16), keeps the
+ * most 256 grids and 1 GiB; 96 iterations each) once per candidate with
+ * sor_batch_solve_f64 (bits 64: the fixed depth of 6 x 16..384 rows) or the
+ * inner sweeps of sor_batch_solve_mixed (bits 32 or 16: 2, 3 or 4
+ * iterations per pass x 16..384 rows), keeps the
  * fastest in the context's batched tuning table for n's size class (used by
  * batched solves and by nothing else) and returns it in *best (may be NULL).
  * n in 8..8192.  Results never depend on the tiling.

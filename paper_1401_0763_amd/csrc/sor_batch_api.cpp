@@ -67,7 +67,14 @@ sor_tiling batch_tiling(sor_ctx *c, int prec, int n) {
     if (it != m.end()) return it->second;
   }
   sor_tiling t = c->tiling[prec];
-  if (t.seg_rows == 0) t.seg_rows = n < 512 ? 64 : (prec == kF64 ? 192 : 96);
+  if (prec == kF64) {
+    // Depth-kBatchT tiles, one wavefront per SIMD: the batch autotuner's
+    // choices on the 512-grid workload were 96-192 rows below n = 512 and
+    // 384 from n = 512 on.
+    if (t.seg_rows == 0) t.seg_rows = n < 512 ? 128 : 384;
+    return t;
+  }
+  if (t.seg_rows == 0) t.seg_rows = n < 512 ? 64 : 96;
   if (n < 512) {
     t.iters_per_pass = std::min(t.iters_per_pass, 4);
     t.seg_rows = std::min(t.seg_rows, 64);

@@ -235,14 +235,16 @@ hipError_t launch_batch_pack(BGrid *grids, int count, int max_n,
                              hipStream_t s);
 hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n,
                                hipStream_t s);
-// Depth of the persistent batched FP64 sweep: the deepest pass whose tile
-// body (with a source term; grids without one read it as zero) keeps two
-// wavefronts per SIMD.  A grid's passes all have the tile geometry of this
-// depth; shorter passes (re-runs, the last iterations before a limit) run in
-// a tail kernel.
-constexpr int kBatchT = 5;
+// Depth of the persistent batched FP64 sweep (its tile body has a source
+// term; grids without one read it as zero).  Measured on 512 grids of sides
+// 64-1024: depth 6 (one wavefront per SIMD) solves the batch in 0.29 s, 0.27
+// s with tuned tiles, against 0.35 s for depth 5 (the deepest with two
+// wavefronts per SIMD) and 0.29 / 0.33 s for depths 7 / 8.  A grid's passes
+// all have the tile geometry of this depth; shorter passes (re-runs, the last
+// iterations before a limit) run in a tail kernel.
+constexpr int kBatchT = 6;
 // Deepest inner pass of the mixed-precision persistent kernel (batched solves
-// and the request server), same rule.
+// and the request server): the deepest that keeps two wavefronts per SIMD.
 constexpr int kMixTMax = 4;
 // Persistent batched sweep (FP64 storage).  The main kernel (tail false)
 // takes its items from q/ring and parks grids that need a shorter pass in

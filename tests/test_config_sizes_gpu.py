@@ -80,8 +80,8 @@ def _batch_vs_oracle(sor, ctx, grids, tol, iters, K):
 @pytest.mark.parametrize("tuned", [False, True])
 def test_c4_grids_fixed_iterations(sor, tuned):
     """33 grids with sides up to 1024, 150 iterations each, checked every
-    iteration, in one persistent launch: with the size rule's tiles (64 rows
-    below n = 512, 192 above), then with tiles from the batched autotuner for
+    iteration, in one persistent launch: with the size rule's tiles (128 rows
+    below n = 512, 384 above), then with tiles from the batched autotuner for
     the classes of n = 1024 and n = 700."""
     ctx = sor.Context(0)
     try:
