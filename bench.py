@@ -248,7 +248,7 @@ def mixed_run(sor, ctx, torch, g, b, f, bits, max_outer, b_inf, exact, scale, re
         bw.append(rinf / (8.0 * float(u.abs().max()) + b_inf))
     k_bw = next((k + 1 for k, x in enumerate(bw) if x <= 1e-10), None)
     out = {"secs": round(dt, 3), "outer_steps": r.outer_steps,
-           "inner_iters_per_step": (max(n // 2, 1) + 3) // 4 * 4,
+           "inner_iters_per_step": (max(n // 2, 1) + 5) // 6 * 6,
            "rel_history": [float(x) for x in r.hist],
            "backward_error_history": [float(f"{x:.3e}") for x in bw],
            "best_rel_residual": float(min(r.hist)),
@@ -272,7 +272,7 @@ def form_mixed(sor, ctx, torch):
            "note": "refinement step k is timed as k/steps of the whole run (every step "
                    "does the same work); backward error = ||r||_inf / (8 ||u||_inf + "
                    "||b||_inf) in the h*h-scaled system; inner iterations per correction: "
-                   "the default, n/2 rounded up to a multiple of 4"}
+                   "the default, n/2 rounded up to a multiple of 6"}
     for n in (4096, 1024):
         g = poisson_manufactured(n, seed=3)
         b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
@@ -618,11 +618,12 @@ def form_serving(sor, ctx, torch, count, burst):
     import numpy as np
     from workloads import ServingStream
     tol = 1e-8
-    # n inner iterations per correction (a multiple of 4 rounded up): fewer,
-    # longer corrections than the library default (about n/2) pay off here,
-    # since every correction's phase changes meet the time-slice boundaries;
-    # measured 113-122 solves/s against 99-110 for the default and 93 for 2n.
-    inner = lambda n: (n + 3) // 4 * 4
+    # n inner iterations per correction (rounded up to a multiple of the
+    # persistent kernel's depth, 6): fewer, longer corrections than the
+    # library default (about n/2) pay off here, since every correction's
+    # phase changes meet the time-slice boundaries; measured (at depth 4)
+    # 113-122 solves/s against 99-110 for the default and 93 for 2n.
+    inner = lambda n: (n + 5) // 6 * 6
     srv = sor.Server(0, inner_bits=32, hbm_budget=64 << 30, max_slots=128, slice_ms=2.0)
     try:
         # Saturated rate: a closed-loop burst of `burst` requests.

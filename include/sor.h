@@ -121,11 +121,11 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * and FP32 Laplace problems on gfx950), else 6; batched FP64 solves always
  * run passes of 6 iterations (shorter ones only to finish a solve), and the
  * inner sweeps of batched and served mixed solves use the context's depth
- * capped at 4.  Until seg_rows is set, each plain solve picks it from the
+ * capped at 6.  Until seg_rows is set, each plain solve picks it from the
  * grid side, so that a pass has about as many tiles as the device holds
  * resident wavefronts of the pass kernel (2*2*iters_per_pass..768 rows);
- * batched FP64 solves use 128 rows below n = 512, else 384, and mixed inner
- * sweeps 64 rows below n = 512, else 96.  An
+ * batched FP64 solves and mixed inner sweeps use 128 rows below n = 512,
+ * else 384.  An
  * autotuned entry for the grid's size class (sor_autotune for plain solves,
  * sor_autotune_batch for batched ones) takes precedence.  Results do not
  * depend on the tiling. */
@@ -376,10 +376,10 @@ sor_status sor_residual_f64(sor_ctx *ctx, const double *u,
  *   bounds the infinity norm of the inverse of the unscaled 5-point operator
  *   on the unit square, keeping the scaled correction below about 2^14);
  *   the correction is added as u + (double)e * 2^-p.
- *   inner_iters <= 0 selects n/2 rounded up to a multiple of 4 (at least 4):
+ *   inner_iters <= 0 selects n/2 rounded up to a multiple of 6 (at least 6):
  *   on Poisson problems from 256^2 to 4096^2 about n/2 reaches a relative
  *   residual of 1e-8 in the least time of n/8 .. 2n (each correction lowers
- *   rel about 20-fold); multiples of 4 let batched and served solves run
+ *   rel about 20-fold); multiples of 6 let batched and served solves run
  *   their faster fixed-depth kernel.
  *   binary16 storage is accepted for n <= 1024 only (SOR_EINVAL above; the
  *   same limit holds for the batched solve and the request server).  Its
@@ -471,8 +471,8 @@ sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best)
  * scratch batch of identical n x n grids (enough for about 4096 tiles, at
  * most 256 grids and 1 GiB; 96 iterations each) once per candidate with
  * sor_batch_solve_f64 (bits 64: the fixed depth of 6 x 16..384 rows) or the
- * inner sweeps of sor_batch_solve_mixed (bits 32 or 16: 2, 3 or 4
- * iterations per pass x 16..384 rows), keeps the
+ * inner sweeps of sor_batch_solve_mixed (bits 32 or 16: passes of 6
+ * iterations x 16..384 rows), keeps the
  * fastest in the context's batched tuning table for n's size class (used by
  * batched solves and by nothing else) and returns it in *best (may be NULL).
  * n in 8..8192.  Results never depend on the tiling.
@@ -495,7 +495,7 @@ typedef struct sor_mixed_desc {
                                  |e| is below corr_tol                      */
     int64_t max_outer;        /* >= 0 corrections                           */
     int64_t inner_iters;      /* > 0 inner iterations per correction
-                                 (<= 0: n/2 rounded up to a multiple of 4)  */
+                                 (<= 0: n/2 rounded up to a multiple of 6)  */
 } sor_mixed_desc;
 
 /*
@@ -537,7 +537,7 @@ typedef struct sor_request {
     double rel_tol;
     double corr_tol;
     int64_t max_outer;
-    int64_t inner_iters;      /* <= 0: n/2 rounded up to a multiple of 4    */
+    int64_t inner_iters;      /* <= 0: n/2 rounded up to a multiple of 6    */
 } sor_request;
 
 typedef struct sor_request_info {

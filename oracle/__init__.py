@@ -195,7 +195,7 @@ def mixed(u0, bdy, f, omega, rel_tol, max_outer, inner_bits=32,
     lib = _load()
     n = int(np.asarray(bdy).size // 4)
     if inner_iters is None:
-        inner_iters = (max(1, n // 2) + 3) // 4 * 4     # the library's default count
+        inner_iters = (max(1, n // 2) + 5) // 6 * 6     # the library's default count
     u, b, ff = _grid_args(n, u0, bdy, f, np.float64)
     outer = ctypes.c_int64(0)
     rel = ctypes.c_double(0.0)

@@ -74,11 +74,9 @@ sor_tiling batch_tiling(sor_ctx *c, int prec, int n) {
     if (t.seg_rows == 0) t.seg_rows = n < 512 ? 128 : 384;
     return t;
   }
-  if (t.seg_rows == 0) t.seg_rows = n < 512 ? 64 : 96;
-  if (n < 512) {
-    t.iters_per_pass = std::min(t.iters_per_pass, 4);
-    t.seg_rows = std::min(t.seg_rows, 64);
-  }
+  // Mixed inner sweeps: passes of the context's depth (6 unless set, the
+  // persistent kernel's fixed depth), tiles as for FP64.
+  if (t.seg_rows == 0) t.seg_rows = n < 512 ? 128 : 384;
   return t;
 }
 
@@ -491,10 +489,10 @@ sor_status sor_autotune_batch(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *b
   const auto saved = table.find(cls) != table.end() ? table[cls] : sor_tiling{0, 0};
   sor_tiling bt{4, 64};
   double best_t = INFINITY;
-  // Batched FP64 passes have a fixed depth: only the tile height is searched
-  // for them.
-  const std::vector<int> depths = prec == kF64 ? std::vector<int>{kBatchT}
-                                                : std::vector<int>{2, 3, 4};
+  // Batched passes have a fixed depth (FP64) or run fastest at the
+  // persistent kernel's fixed depth (mixed inner sweeps): only the tile
+  // height is searched.
+  const std::vector<int> depths{prec == kF64 ? kBatchT : kMixTMax};
   for (int T : depths) {
     for (int seg : {16, 32, 48, 64, 96, 128, 192, 256, 384}) {
       if (he != hipSuccess) break;

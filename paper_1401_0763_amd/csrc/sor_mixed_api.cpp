@@ -203,13 +203,14 @@ struct MixRunner {
   }
 
   // Kernel for a launch over the listed slots: the run-time-depth one when
-  // some grid's inner iteration count is not a multiple of the fixed depth,
-  // and for binary16 storage (whose fixed-depth kernel holds one wavefront
-  // per SIMD, the run-time-depth one two).
+  // some grid's passes are shallower than the fixed depth (a depth set on
+  // the context or tuned for its size class) or its inner iteration count
+  // is not a multiple of it, and for binary16 storage (whose fixed-depth
+  // kernel holds one wavefront per SIMD, the run-time-depth one two).
   bool need_dyn(const std::vector<int> &active) const {
     if (prec_lo == kF16) return true;
     for (int s : active)
-      if (h_grids[s].inner_iters % kMixTMax != 0) return true;
+      if (h_grids[s].T != kMixTMax || h_grids[s].inner_iters % kMixTMax != 0) return true;
     return false;
   }
 

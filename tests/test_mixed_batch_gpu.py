@@ -1,7 +1,7 @@
 """GPU parity of mixed-precision batched solves and of the request server.
 
 Grids and requests that pass no inner iteration count get the library's
-default (n/2 rounded up to a multiple of 4); the oracle's default is the same
+default (n/2 rounded up to a multiple of 6); the oracle's default is the same
 count.  Each
 grid, whether solved in a batch or served among other requests, must equal
 the CPU oracle's defect-correction solve of that grid alone bit for bit at
@@ -70,6 +70,25 @@ def test_mixed_batch_fixed_corrections_bitwise(sor, ctx, bits, odd):
         assert r.outer_steps == ref.outer_steps == outer, (k, r)
         assert bitwise(u.cpu().numpy(), ref.u), (k, g.n)
         assert abs(r.rel_residual - ref.rel_residual) <= 1e-9 * ref.rel_residual + 1e-300
+
+
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_mixed_batch_shallower_context_depth(sor, ctx, depth):
+    """A depth set on the context below the fixed depth of the persistent
+    kernel: the inner passes must still apply exactly the counted iterations
+    (the run-time-depth kernel), so the result is the oracle's bit for bit,
+    with default inner counts and with odd ones."""
+    ctx.set_tiling(32, depth, 0)
+    grids = grids_for(5, [4, 33, 100, 130, 250, 520])
+    for inner in (None, 13):
+        us = [dev(g.u0) for g in grids]
+        specs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 0.0, 2, inner or 0)
+                 for u, g in zip(us, grids)]
+        res = sor.batch_solve_mixed(specs, 32, ctx=ctx)
+        for k, (g, r, u) in enumerate(zip(grids, res, us)):
+            ref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, 2, 32, inner)
+            assert r.outer_steps == ref.outer_steps == 2, (k, r)
+            assert bitwise(u.cpu().numpy(), ref.u), (depth, inner, k, g.n)
 
 
 @pytest.mark.parametrize("bits,tol", [(32, 1e-11), (16, 1e-9)])
