@@ -763,6 +763,13 @@ sor_status sor_solve_blockpar_f64(sor_ctx *c, double *u, const double *bdy, cons
   if (block_rows < 1 || block_cols < 1)
     return fail(c, SOR_EINVAL, "block shape %d x %d: both sides must be >= 1", block_rows,
                 block_cols);
+  // A side of n or more puts every interior row (column) in one block: the
+  // same iteration as a side of n, which keeps the kernels' block arithmetic
+  // far from overflow.
+  if (n > 0) {
+    block_rows = std::min(block_rows, n);
+    block_cols = std::min(block_cols, n);
+  }
   return solve_ordered(c, SOR_ORDER_BLOCK_PARALLEL, u, bdy, rhs, n, omega, block_rows,
                        block_cols, tol, max_iters, check_every, stream, out, hist);
 }

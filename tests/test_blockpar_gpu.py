@@ -164,6 +164,17 @@ def test_limits_match_the_other_solvers(sor, ctx):
     assert_bitwise(np.array(res.hist), np.array(r3.hist), "one-cell blocks vs Jacobi hist")
 
 
+def test_block_sides_beyond_the_grid(sor, ctx):
+    """Block sides up to the largest int32 behave as sides of n (one block
+    row or column): bit for bit the oracle, and red-black for both."""
+    n = 90
+    g = random_small(91, n, with_f=True, nonzero_u0=True)
+    big = 2**31 - 1
+    for br, bc in ((big, big), (big, 7), (8, big)):
+        _say(f"blockpar blocks {br}x{bc} n={n}")
+        check(sor, ctx, g, br, bc, 1.3, 12, f"{br}x{bc}")
+
+
 def test_bench_grid_4096(sor, ctx):
     """The 4096^2 bench grid with 128 x 128 blocks, 6 iterations at the
     default tiling, whole grid compared."""
