@@ -97,6 +97,40 @@ def test_c4_grids_fixed_iterations(sor, tuned):
         ctx.close()
 
 
+def test_c4_whole_batch_every_grid(sor):
+    """The whole batched workload (512 grids, sides 64..1024, FP64 to max |du|
+    < 1e-8 checked every iteration, then FP32 + FP64 refinement with two
+    corrections of the default inner count) in one launch each: every grid's
+    stop iteration, final change and values equal the oracle's standalone
+    solve bit for bit."""
+    grids = batch_grids(512, 64, 1024, seed=4, tol=1e-8)
+    ctx = sor.Context(0)
+    try:
+        us = [torch.zeros((g.n, g.n), dtype=torch.float64, device="cuda") for g in grids]
+        specs = [sor.GridSpec(u, dev(g.bdy), dev(g.f), g.omega, 1e-8, 200000, 1)
+                 for u, g in zip(us, grids)]
+        res = sor.batch_solve_f64(specs, ctx=ctx)
+        um = [torch.zeros((g.n, g.n), dtype=torch.float64, device="cuda") for g in grids]
+        mspecs = [sor.MixedSpec(u, dev(g.bdy), dev(g.f), g.omega, 0.0, 0.0, 2, 0)
+                  for u, g in zip(um, grids)]
+        mres = sor.batch_solve_mixed(mspecs, 32, ctx=ctx)
+        got = [u.cpu().numpy() for u in us]
+        gotm = [u.cpu().numpy() for u in um]
+    finally:
+        ctx.close()
+    t0 = time.time()
+    for k, g in enumerate(grids):
+        ref = oracle.sor_f64(g.u0, g.bdy, g.f, g.omega, 1e-8, 200000, 1, threads=16)
+        assert (res[k].status, res[k].iterations) == (ref.status, ref.iterations), (k, g.n)
+        assert bits(res[k].final_max_delta) == bits(ref.final_max_delta), (k, g.n)
+        assert bitwise(got[k], ref.u), (k, g.n)
+        mref = oracle.mixed(g.u0, g.bdy, g.f, g.omega, 0.0, 2, 32, threads=16)
+        assert mres[k].outer_steps == mref.outer_steps == 2, (k, g.n)
+        assert bitwise(gotm[k], mref.u), ("mixed", k, g.n)
+        if k % 64 == 63:
+            _say(f"whole batch: {k + 1} grids equal to the oracle ({time.time() - t0:.0f} s)")
+
+
 def test_c4_large_grids_to_tolerance(sor):
     """Three grids of sides 802..1024 solved to max |du| < 1e-8 (checked every
     iteration) among small ones: stop iterations of several thousand, equal
