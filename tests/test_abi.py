@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -97,3 +98,12 @@ def test_omega_opt_host_function():
     # the closed form of the survey's table (n = 256 and 4096)
     assert abs(lib.sor_omega_opt(256) - 1.975847650301681) < 1e-15
     assert abs(lib.sor_omega_opt(4096) - 1.998467568850995) < 1e-15
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: --gpus above 1 exits with status 2 and
+    a message, before touching a device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
