@@ -41,8 +41,9 @@ and, each against plain one-grid-at-a-time FP64 on the same GPU:
            correction around FP32 inner sweeps vs plain FP64 SOR, each run to
            its accuracy floor: relative residual, normwise backward error,
            error against the exact discrete solution (DST-I) and difference
-           from the FP64 SOR result; binary16 inner storage at 1024^2 (the
-           largest side it accepts) beside FP32 there;
+           from the FP64 SOR result, update rates (GLUP/s) and algorithmic
+           bandwidth; binary16 inner storage at 1024^2 (the largest side it
+           accepts) beside FP32 there;
   batched  512 grids, sides log-uniform in [64, 1024] (seed 4), f = N(0,1) on
            odd grids, omega_opt, tol 1e-8: one persistent launch, FP64 (with
            the size rule's tiles and with autotuned tiles) and
@@ -247,8 +248,18 @@ def mixed_run(sor, ctx, torch, g, b, f, bits, max_outer, b_inf, exact, scale, re
         _, _, rinf = sor.residual_f64(u, b, f, ctx=ctx)
         bw.append(rinf / (8.0 * float(u.abs().max()) + b_inf))
     k_bw = next((k + 1 for k, x in enumerate(bw) if x <= 1e-10), None)
+    inner = (max(n // 2, 1) + 5) // 6 * 6
+    lups = r.outer_steps * inner * n * n
+    esz = 4 if bits == 32 else 2
+    # Algorithmic bytes: an inner update reads the correction and the inner
+    # right-hand side and writes the correction (storage precision); a
+    # correction's FP64 steps read u and h^2 f and write the inner right-hand
+    # side, then read u and e and write u.
+    alg = lups * 3 * esz + r.outer_steps * n * n * (2 * (16 + esz))
     out = {"secs": round(dt, 3), "outer_steps": r.outer_steps,
-           "inner_iters_per_step": (max(n // 2, 1) + 5) // 6 * 6,
+           "inner_iters_per_step": inner,
+           "inner_glups": round(lups / dt / 1e9, 1),
+           "hbm_equiv_GBs": round(alg / dt / 1e9, 1),
            "rel_history": [float(x) for x in r.hist],
            "backward_error_history": [float(f"{x:.3e}") for x in bw],
            "best_rel_residual": float(min(r.hist)),
@@ -272,7 +283,11 @@ def form_mixed(sor, ctx, torch):
            "note": "refinement step k is timed as k/steps of the whole run (every step "
                    "does the same work); backward error = ||r||_inf / (8 ||u||_inf + "
                    "||b||_inf) in the h*h-scaled system; inner iterations per correction: "
-                   "the default, n/2 rounded up to a multiple of 6"}
+                   "the default, n/2 rounded up to a multiple of 6; glups / inner_glups: "
+                   "(inner) red-black updates per second of the whole solve (FP64: its "
+                   "residual checks every 2000 iterations included); hbm_equiv_GBs: "
+                   "algorithmic bytes per second (FP64 Poisson update 24 B; inner update "
+                   "3 stored values; per correction 2 x (16 B + one stored value) per cell)"}
     for n in (4096, 1024):
         g = poisson_manufactured(n, seed=3)
         b = torch.tensor(g.bdy, dtype=torch.float64, device="cuda")
@@ -294,7 +309,10 @@ def form_mixed(sor, ctx, torch):
             best = min(best, rel)
         ref = u64.cpu().numpy()
         key = "" if n == 4096 else f"_{n}"
-        rec = {"iterations": trace[-1][1], "secs": round(trace[-1][0], 3),
+        its = trace[-1][1]
+        rec = {"iterations": its, "secs": round(trace[-1][0], 3),
+               "glups": round(its * n * n / trace[-1][0] / 1e9, 1),
+               "hbm_equiv_GBs": round(24.0 * its * n * n / trace[-1][0] / 1e9, 1),
                "best_rel_residual": best,
                "secs_to": {str(t): time_to(trace, t) for t in targets}}
         rec.update(accuracy(sor, ctx, u64, b, f, b_inf, exact, scale))
