@@ -165,8 +165,16 @@ sor_status sor_ctx_get_profile(const sor_ctx *ctx, double *kernel_ms,
  *   out         receives the outcome (required)
  *   max_hist    optional HOST array of max_iters doubles: entry k-1 receives
  *               the change of iteration k for k = 1..out->iterations.
+ *               Without it, each sweep pass forms only the changes of the
+ *               check iterations it holds (one pass variant per position of
+ *               the check in the pass, and one forming none), which the
+ *               stopping rule reads; results are the same either way.
  * Returns SOR_OK (converged), SOR_NOT_CONVERGED, SOR_ENONFINITE (u holds the
- * non-finite iterate), SOR_EINVAL, SOR_ENOMEM or SOR_EDEVICE.
+ * non-finite iterate; out->final_max_delta is the change of the last
+ * iteration of the pass that found it, or NaN when that pass formed none),
+ * SOR_EINVAL, SOR_ENOMEM or SOR_EDEVICE.  A grid value that is not finite is
+ * what SOR_ENONFINITE reports; a change that overflows between two finite
+ * values is an ordinary (infinite) change, as the oracle counts it.
  */
 sor_status sor_solve_f64(sor_ctx *ctx, double *u, const double *boundary,
                          const double *rhs, int32_t n, double omega, double tol,

@@ -130,6 +130,25 @@ int pass_depth(long long left, int T) {
   return 1;
 }
 
+// The mx of a red-black pass applying iterations it0+1 .. it0+T under sc:
+// T when no maximum is read (no check iteration among them, or the pass
+// reports nothing), the check iteration's index (from 0) when there is
+// exactly one, and -1 when there are several or every iteration's change
+// is wanted.
+int pass_maxima(long long it0, int T, const Sched &sc, bool every, bool reported) {
+  if (!reported) return T;
+  if (every) return -1;
+  int pos = T, checks = 0;
+  for (int t = 0; t < T; ++t) {
+    const long long it = it0 + t + 1;
+    if (it % sc.check_every == 0 || it == sc.max_iters) {
+      pos = t;
+      ++checks;
+    }
+  }
+  return checks > 1 ? -1 : pos;
+}
+
 GridView view_for(const GridView &base, int prec, int T, int ord = 0) {
   GridView v = base;
   const BlockGeom g = block_geom(prec, T, ord);
@@ -229,7 +248,8 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
       } else if (simple) {
         HIP_TRY(c, launch_simple_iteration(prec, v, ctl, sc, s));
       } else {
-        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord, bs));
+        const int mx = ord ? -1 : pass_maxima(done, Tp, sc, hist != nullptr, true);
+        HIP_TRY(c, launch_blocked_pass(prec, Tp, v, ctl, sc, s, ord, bs, mx));
         std::swap(cur, oth);
       }
       recs[nrecs++] = PassRec{v.in, v.out, done, Tp};
@@ -292,7 +312,9 @@ sor_status run_sweeps(sor_ctx *c, int prec, const Layout &L, void *A, void *B,
           GridView v = view_for(base, prec, t, ord);
           v.in = src;
           v.out = dst;
-          HIP_TRY(c, launch_blocked_pass(prec, t, v, rctl, tentative ? rsc : sc, s, ord, bs));
+          // The re-run reads no maxima: its rule never passes.
+          const int mx = ord ? -1 : t;
+          HIP_TRY(c, launch_blocked_pass(prec, t, v, rctl, tentative ? rsc : sc, s, ord, bs, mx));
           ++reruns;
           *result_grid = dst;
           std::swap(src, dst);

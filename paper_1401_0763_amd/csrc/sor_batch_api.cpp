@@ -420,11 +420,13 @@ sor_status sor_autotune(sor_ctx *c, int32_t bits, int32_t n, sor_tiling *best) {
       v.nstrips = (n + 1 + gm.CW - 1) / gm.CW;
       v.nseg = (n + 1 + seg - 1) / seg;
       const int reps = 3;
-      if (e == hipSuccess) e = launch_blocked_pass(prec, T, v, nullptr, sc, s);   // warm-up
+      // Timed as a solve's passes run: forming the maxima of one iteration.
+      const int mx = T - 1;
+      if (e == hipSuccess) e = launch_blocked_pass(prec, T, v, nullptr, sc, s, 0, {}, mx);
       if (e == hipSuccess) e = hipEventRecord(e0, s);
       for (int k = 0; k < reps && e == hipSuccess; ++k) {
         std::swap(v.in, *(const void **)&v.out);
-        e = launch_blocked_pass(prec, T, v, nullptr, sc, s);
+        e = launch_blocked_pass(prec, T, v, nullptr, sc, s, 0, {}, mx);
       }
       if (e == hipSuccess) e = hipEventRecord(e1, s);
       if (e == hipSuccess) e = hipEventSynchronize(e1);

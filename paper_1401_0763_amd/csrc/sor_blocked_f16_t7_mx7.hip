@@ -1,0 +1,11 @@
+// Blocked red-black SOR pass, binary16 storage, 7 iterations per pass, forming
+// no maxima (one kernel each;
+// iterations counted from 0 within the pass).
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF16, 7, 0, 7>(const GridView &, Ctl *,
+                                                 const Sched &, hipStream_t,
+                                                 const BlockShape &);
+template int blocked_blocks_per_cu<kF16, 7, 0, 7>(bool);
+}  // namespace sor

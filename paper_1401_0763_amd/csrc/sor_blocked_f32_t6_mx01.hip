@@ -1,0 +1,13 @@
+// Blocked red-black SOR pass, FP32 storage, 6 iterations per pass, forming
+// the maxima of iteration 0 alone / the maxima of iteration 1 alone (one kernel each;
+// iterations counted from 0 within the pass).
+#include "sor_kernels.h"
+
+namespace sor {
+template hipError_t launch_blocked_PT<kF32, 6, 0, 0>(const GridView &, Ctl *,
+                                                 const Sched &, hipStream_t,
+                                                 const BlockShape &);
+template hipError_t launch_blocked_PT<kF32, 6, 0, 1>(const GridView &, Ctl *,
+                                                 const Sched &, hipStream_t,
+                                                 const BlockShape &);
+}  // namespace sor

@@ -351,6 +351,53 @@ hipError_t launch_fill_zero(int prec, void *A, int64_t pitch, int n, hipStream_t
 SOR_EXTERN_BLOCKED_ALL(kF64)
 SOR_EXTERN_BLOCKED_ALL(kF32)
 SOR_EXTERN_BLOCKED_ALL(kF16)
+// Red-black passes that form the maxima of one iteration (MX = 0..T-1) or
+// of none (MX = T), in the sor_blocked_*_t*_mx*.hip units: FP64 and FP32 at
+// depths 6 and 7 (the automatic depths), and for binary16 inner sweeps,
+// which check only at their last iteration, the variant without maxima.
+#define SOR_EXTERN_MX(P, T, MX)                                                \
+  extern template hipError_t launch_blocked_PT<P, T, 0, MX>(                   \
+      const GridView &, Ctl *, const Sched &, hipStream_t, const BlockShape &);
+#define SOR_EXTERN_MX6(P)                                                      \
+  SOR_EXTERN_MX(P, 6, 0) SOR_EXTERN_MX(P, 6, 1) SOR_EXTERN_MX(P, 6, 2)         \
+  SOR_EXTERN_MX(P, 6, 3) SOR_EXTERN_MX(P, 6, 4) SOR_EXTERN_MX(P, 6, 5)         \
+  SOR_EXTERN_MX(P, 6, 6)
+#define SOR_EXTERN_MX7(P)                                                      \
+  SOR_EXTERN_MX(P, 7, 0) SOR_EXTERN_MX(P, 7, 1) SOR_EXTERN_MX(P, 7, 2)         \
+  SOR_EXTERN_MX(P, 7, 3) SOR_EXTERN_MX(P, 7, 4) SOR_EXTERN_MX(P, 7, 5)         \
+  SOR_EXTERN_MX(P, 7, 6) SOR_EXTERN_MX(P, 7, 7)
+SOR_EXTERN_MX6(kF64) SOR_EXTERN_MX7(kF64)
+SOR_EXTERN_MX6(kF32) SOR_EXTERN_MX7(kF32)
+SOR_EXTERN_MX(kF16, 6, 6) SOR_EXTERN_MX(kF16, 7, 7)
+extern template int blocked_blocks_per_cu<kF64, 6, 0, 5>(bool);
+extern template int blocked_blocks_per_cu<kF64, 7, 0, 6>(bool);
+extern template int blocked_blocks_per_cu<kF32, 6, 0, 5>(bool);
+extern template int blocked_blocks_per_cu<kF32, 7, 0, 6>(bool);
+extern template int blocked_blocks_per_cu<kF16, 6, 0, 6>(bool);
+extern template int blocked_blocks_per_cu<kF16, 7, 0, 7>(bool);
+
+// Which maxima variants a (precision, depth) has: 2 one per iteration and
+// none, 1 none only, 0 only the pass forming every maximum.
+constexpr int rb_mx_variants(int P, int T) {
+  return (T == 6 || T == 7) ? (P == kF16 ? 1 : 2) : 0;
+}
+
+// The red-black pass of depth T forming the maxima that mx selects (-1
+// every iteration, 0..T-1 that one, T none), or, where that variant is
+// not built, every maximum (a superset: the stopping rule reads the same
+// values).
+template <int P, int T, int M = 0>
+static hipError_t launch_rb(int mx, const GridView &v, Ctl *ctl, const Sched &sc,
+                            hipStream_t s) {
+  if constexpr (rb_mx_variants(P, T) == 2 && M < T) {
+    if (mx == M) return launch_blocked_PT<P, T, 0, M>(v, ctl, sc, s);
+    return launch_rb<P, T, M + 1>(mx, v, ctl, sc, s);
+  } else {
+    if constexpr (rb_mx_variants(P, T) >= 1)
+      if (mx == T) return launch_blocked_PT<P, T, 0, T>(v, ctl, sc, s);
+    return launch_blocked_PT<P, T>(v, ctl, sc, s);
+  }
+}
 #define SOR_EXTERN_BLOCKED_ORD(T, ORD)                                         \
   extern template hipError_t launch_blocked_PT<kF64, T, ORD>(                  \
       const GridView &, Ctl *, const Sched &, hipStream_t, const BlockShape &); \
@@ -418,18 +465,29 @@ static int blocked_blocks_per_cu_ord(int T, bool pois) {
 
 template <int P>
 static hipError_t launch_blocked_P(int T, const GridView &v, Ctl *ctl,
-                                   const Sched &sc, hipStream_t s) {
+                                   const Sched &sc, hipStream_t s, int mx) {
   switch (T) {
     case 1: return launch_blocked_PT<P, 1>(v, ctl, sc, s);
     case 2: return launch_blocked_PT<P, 2>(v, ctl, sc, s);
     case 3: return launch_blocked_PT<P, 3>(v, ctl, sc, s);
     case 4: return launch_blocked_PT<P, 4>(v, ctl, sc, s);
     case 5: return launch_blocked_PT<P, 5>(v, ctl, sc, s);
-    case 6: return launch_blocked_PT<P, 6>(v, ctl, sc, s);
-    case 7: return launch_blocked_PT<P, 7>(v, ctl, sc, s);
+    case 6: return launch_rb<P, 6>(mx, v, ctl, sc, s);
+    case 7: return launch_rb<P, 7>(mx, v, ctl, sc, s);
     case 8: return launch_blocked_PT<P, 8>(v, ctl, sc, s);
   }
   return hipErrorInvalidValue;
+}
+
+// Occupancy of the pass a solve mostly runs: with a maxima variant, the one
+// forming the maxima of its last iteration (a solve checking every T or
+// more iterations has at most one check per pass), or, with binary16
+// storage, the one forming none (inner sweeps check only at their end).
+template <int P, int T>
+static int blocked_blocks_per_cu_rb(bool pois) {
+  if constexpr (rb_mx_variants(P, T) == 2) return blocked_blocks_per_cu<P, T, 0, T - 1>(pois);
+  else if constexpr (rb_mx_variants(P, T) == 1) return blocked_blocks_per_cu<P, T, 0, T>(pois);
+  else return blocked_blocks_per_cu<P, T>(pois);
 }
 
 template <int P>
@@ -440,8 +498,8 @@ static int blocked_blocks_per_cu_P(int T, bool pois) {
     case 3: return blocked_blocks_per_cu<P, 3>(pois);
     case 4: return blocked_blocks_per_cu<P, 4>(pois);
     case 5: return blocked_blocks_per_cu<P, 5>(pois);
-    case 6: return blocked_blocks_per_cu<P, 6>(pois);
-    case 7: return blocked_blocks_per_cu<P, 7>(pois);
+    case 6: return blocked_blocks_per_cu_rb<P, 6>(pois);
+    case 7: return blocked_blocks_per_cu_rb<P, 7>(pois);
     case 8: return blocked_blocks_per_cu<P, 8>(pois);
   }
   return 0;
@@ -476,7 +534,7 @@ bool blocked_ord_T_supported(int ord, int T) {
 
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s, int ord,
-                               const BlockShape &bs) {
+                               const BlockShape &bs, int mx) {
   if (ord) {
     if (prec != kF64) return hipErrorInvalidValue;
     switch (ord) {
@@ -488,9 +546,9 @@ hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
     return hipErrorInvalidValue;
   }
   switch (prec) {
-    case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s);
-    case kF32: return launch_blocked_P<kF32>(T, v, ctl, sc, s);
-    case kF16: return launch_blocked_P<kF16>(T, v, ctl, sc, s);
+    case kF64: return launch_blocked_P<kF64>(T, v, ctl, sc, s, mx);
+    case kF32: return launch_blocked_P<kF32>(T, v, ctl, sc, s, mx);
+    case kF16: return launch_blocked_P<kF16>(T, v, ctl, sc, s, mx);
   }
   return hipErrorInvalidValue;
 }

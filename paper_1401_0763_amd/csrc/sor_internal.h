@@ -282,12 +282,15 @@ hipError_t launch_fill_zero(int prec, void *grid, int64_t pitch, int n,
 // 1..kTMax, every precision), four-colour (ord 1, T in 1..kTMaxC4, FP64),
 // Jacobi (ord 2, T in 1..kTMax, FP64) or block-parallel red-black (ord 3, or
 // 4 when bs.cols is even or at least n; T in 1..kTMax, FP64, blocks of shape
-// bs); the view's nstrips/nseg must match T and the ordering.  ctl == nullptr runs without maxima, verdict or early
-// exit.
+// bs); the view's nstrips/nseg must match T and the ordering.  ctl ==
+// nullptr runs without verdict or early exit.  mx (red-black) names the
+// iterations of the pass whose maxima the stopping rule will read: -1 all,
+// 0..T-1 that one, T none; a pass that forms more than these (every
+// variant not built) reports the same values for them.
 constexpr int kTMaxC4 = 5;
 hipError_t launch_blocked_pass(int prec, int T, const GridView &v, Ctl *ctl,
                                const Sched &sc, hipStream_t s, int ord = 0,
-                               const BlockShape &bs = BlockShape{});
+                               const BlockShape &bs = BlockShape{}, int mx = -1);
 bool blocked_T_supported(int T);
 bool blocked_ord_T_supported(int ord, int T);
 // Pass-kernel workgroups (wavefronts) resident per CU; 0 if the query fails.

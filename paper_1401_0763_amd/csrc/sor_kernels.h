@@ -101,12 +101,15 @@ __device__ __forceinline__ int ctl_stopped(const Ctl *ctl) {
 // Publish this wave's per-iteration maxima (already wave-reduced, in lane 0)
 // and, if it is the last wave of the pass, evaluate the stopping rule for the
 // pass's iterations (Algorithm 1), record each iteration's change, and reset
-// the slots for the next pass.
+// the slots for the next pass.  last_formed is false for a pass that formed
+// no maximum for its last iteration: a non-finite grid then reports NaN as
+// its change.
 template <int T>
 __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
                                             const double (&mx)[T], int t_run,
                                             bool bad, int slot,
-                                            unsigned waves_total) {
+                                            unsigned waves_total,
+                                            bool last_formed = true) {
   const int lane = threadIdx.x & 63;
   const bool anybad = __ballot(bad) != 0;
   unsigned prev = 0;
@@ -173,7 +176,7 @@ __device__ __forceinline__ void report_pass(Ctl *ctl, const Sched &sc,
       } else {
         stop = 2;
         ctl->stop_iter = it0 + t_run;
-        ctl->stop_max = it_max[t_run - 1];
+        ctl->stop_max = last_formed ? it_max[t_run - 1] : __builtin_nan("");
       }
     }
     ctl->it_base = it0 + t_run;
@@ -217,15 +220,26 @@ __device__ __forceinline__ Vec<P> buf_load(__amdgpu_buffer_rsrc_t r, unsigned vo
   }
 }
 
+// The store's SGPR offset field is the constant 0 and the row offset goes
+// into the per-lane offset (the sum stays below 2^32, and a lane whose
+// offset carries kDrop stays beyond the extent).  A store of more than 8
+// bytes reads its data registers after it issues, so a vector instruction
+// that overwrites them at once needs a wait state between the two; the
+// compiler inserts it only when the SGPR offset is not a register.  With a
+// register there, the register allocator reused a dead data register for
+// the next instruction's result right behind the store, and at 4096^2
+// some stored cells got a wrong low word, in different cells from run to
+// run.
 template <int P, int AUX = kCohDefault>
 __device__ __forceinline__ void buf_store(const Vec<P> &x, __amdgpu_buffer_rsrc_t r,
                                           unsigned voff, unsigned soff) {
+  const int off = (int)(voff + soff);
   if constexpr (sizeof(Vec<P>) == 16) {
     using v4 = unsigned __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4, x), r, (int)voff, (int)soff, AUX);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4, x), r, off, 0, AUX);
   } else {
     using v2 = unsigned __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, x), r, (int)voff, (int)soff, AUX);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2, x), r, off, 0, AUX);
   }
 }
 
@@ -299,13 +313,22 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // out-of-range offset.
 //
 // m[t] receives the largest |u' - u| of iteration t over the tile's core
-// cells (0 in halo lanes).  bad is set when an interior core cell is not
-// finite at the end of the pass, or some maximum is not finite.  Non-finite
-// values are absorbing for interior cells (an infinite cell's next update is
-// inf - inf or NaN, and a NaN stays NaN), so a cell that turns non-finite at
-// any iteration of the pass is non-finite when its row is stored; the maxima
-// alone would miss a NaN made from finite operands (+inf + -inf), because
-// the max drops NaN.  Non-finite inputs are caught when they are packed.
+// cells (0 in halo lanes).  MX (red-black only) names the iterations whose
+// maxima are formed: -1 all of them, 0..T-1 that one alone, T none; the
+// stopping rule reads only the maxima of check iterations, and a pass
+// holds at most one of them when the check interval is at least T, so the
+// change, its weight and the running maximum (three of the update's eight
+// vector instructions) are left out of the other iterations.  m[t] of an
+// iteration left out stays 0.
+//
+// bad is set when an interior core cell is not finite at the end of the
+// pass.  Non-finite values are absorbing for interior cells (an infinite
+// cell's next update is inf - inf or NaN, and a NaN stays NaN), so a cell
+// that turns non-finite at any iteration of the pass is non-finite when its
+// row is stored.  The maxima are no test for it: the max drops NaN (made
+// from finite operands as +inf + -inf), and a change can overflow between
+// two finite values, which Algorithm 1 counts as an ordinary large change.
+// Non-finite inputs are caught when they are packed.
 //
 // DYN (red-black only): the tile has the geometry of depth T but applies only
 // the first s_run (even, 2..2T) half-sweeps, i.e. s_run/2 iterations; the
@@ -313,7 +336,8 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // iterations not applied.  The halo sized for T covers any smaller depth, so
 // the core cells get exactly the s_run/2-iteration result.
 // ---------------------------------------------------------------------------
-template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0, bool DYN = false>
+template <int P, int T, bool POIS, int COH = kCohDefault, int ORD = 0, bool DYN = false,
+          int MX = -1>
 __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
                                              typename PT<P>::ct (&m)[T],
                                              bool &bad, int s_run = 2 * T,
@@ -324,6 +348,8 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   static_assert(ORD == 0 || P == kF64, "other orderings are instantiated for FP64");
   static_assert(!DYN || ORD == 0, "a run-time depth is implemented for red-black passes");
   static_assert(ORD < 3 || PT<P>::V == 2, "block-parallel passes hold one red cell per lane");
+  static_assert(MX == -1 || (ORD == 0 && !DYN && MX >= 0 && MX <= T),
+                "maxima of selected iterations are implemented for fixed-depth red-black passes");
   constexpr int S = order_stages(ORD, T);        // stages (half-sweeps or colour sweeps)
   constexpr int H = order_row_halo(ORD, T);      // halo rows (even)
   constexpr int A = ((S + V - 1) / V) * V;
@@ -567,9 +593,11 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           if constexpr (P == kF16) nu = self + (omc[v] * wr[sq]) * dg;
           else nu = vfma(omc[v] * wr[sq], dg, self);
           if constexpr (P == kF16) nu = (ct)(st)nu;
-          const ct d = vabs(nu - self);
           w[sq][v] = nu;
-          m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
+          if constexpr (MX < 0 || (k >> 1) == MX) {
+            const ct d = vabs(nu - self);
+            m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
+          }
           if constexpr (v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
         } else if constexpr (k + 1 < S) {
@@ -692,16 +720,14 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   }
   bad = bad | (fhi >= high_bits(std::numeric_limits<ct>::infinity()));
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
+  for (int t = 0; t < T; ++t)
     if (!lane_core) m[t] = (ct)0;
-    bad = bad | !__builtin_isfinite(m[t]);
-  }
 }
 
 // One blocked pass over a whole grid: one wavefront per tile, T iterations
 // from g.in into g.out.  With a control block, the pass first exits if an
 // earlier pass met the stopping rule, then reports its maxima.
-template <int P, int T, bool POIS, int ORD>
+template <int P, int T, bool POIS, int ORD, int MX = -1>
 __device__ __forceinline__ void blocked_pass_body(const GridView &g, Ctl *ctl,
                                                   const Sched &sc,
                                                   const BlockShape bs = BlockShape{}) {
@@ -710,19 +736,23 @@ __device__ __forceinline__ void blocked_pass_body(const GridView &g, Ctl *ctl,
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   ct m[T];
   bool bad = false;
-  blocked_tile<P, T, POIS, kCohDefault, ORD>(g, tile, m, bad, 2 * T, bs);
+  blocked_tile<P, T, POIS, kCohDefault, ORD, false, MX>(g, tile, m, bad, 2 * T, bs);
   if (!ctl) return;
-  double mx[T];
+  double it_max[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) mx[t] = wave_max((double)m[t]);
-  report_pass<T>(ctl, sc, mx, T, bad, blockIdx.x % kSlots, gridDim.x);
+  for (int t = 0; t < T; ++t)
+    it_max[t] = (MX < 0 || t == MX) ? wave_max((double)m[t]) : 0.0;
+  report_pass<T>(ctl, sc, it_max, T, bad, blockIdx.x % kSlots, gridDim.x,
+                 MX < 0 || MX == T - 1);
 }
 
-// Red-black passes.
-template <int P, int T, bool POIS>
+// Red-black passes.  MX selects the iterations whose maxima are formed (-1
+// all, 0..T-1 that one, T none); the host launches the variant that forms
+// exactly those the stopping rule will read.
+template <int P, int T, bool POIS, int MX = -1>
 __global__ __launch_bounds__(64) void blocked_pass_kernel(GridView g, Ctl *ctl,
                                                           Sched sc) {
-  blocked_pass_body<P, T, POIS, 0>(g, ctl, sc);
+  blocked_pass_body<P, T, POIS, 0, MX>(g, ctl, sc);
 }
 
 // Four-colour passes.
@@ -859,8 +889,8 @@ __device__ inline bool bq_take(BQueue *q, BItem *ring, int &g, int &tile) {
 }
 
 // The pass kernel of an ordering (for the launchers below).
-template <int P, int T, bool POIS, int ORD> struct PassKernel {
-  static constexpr auto k = blocked_pass_kernel<P, T, POIS>;
+template <int P, int T, bool POIS, int ORD, int MX = -1> struct PassKernel {
+  static constexpr auto k = blocked_pass_kernel<P, T, POIS, MX>;
 };
 template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 1> {
   static constexpr auto k = blocked_pass_c4_kernel<P, T, POIS>;
@@ -875,12 +905,13 @@ template <int P, int T, bool POIS> struct PassKernel<P, T, POIS, 4> {
   static constexpr auto k = blocked_pass_bp_even_kernel<P, T, POIS>;
 };
 
-// Host-side launch of the blocked pass for one (precision, T); each pair is
-// instantiated in its own translation unit so the unrolled bodies compile in
-// parallel.
-template <int P, int T, int ORD = 0>
+// Host-side launch of the blocked pass for one (precision, T, ordering,
+// maxima selection); each is instantiated in its own translation unit so
+// the unrolled bodies compile in parallel.
+template <int P, int T, int ORD = 0, int MX = -1>
 hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
                              hipStream_t s, const BlockShape &bs = BlockShape{}) {
+  static_assert(MX == -1 || ORD == 0, "maxima selection is a red-black variant");
   const dim3 grid((unsigned)v.nstrips * (unsigned)v.nseg);
   if constexpr (ORD >= 3) {
     if (v.F)
@@ -889,22 +920,22 @@ hipError_t launch_blocked_PT(const GridView &v, Ctl *ctl, const Sched &sc,
       hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc, bs);
   } else {
     if (v.F)
-      hipLaunchKernelGGL((PassKernel<P, T, true, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
+      hipLaunchKernelGGL((PassKernel<P, T, true, ORD, MX>::k), grid, dim3(64), 0, s, v, ctl, sc);
     else
-      hipLaunchKernelGGL((PassKernel<P, T, false, ORD>::k), grid, dim3(64), 0, s, v, ctl, sc);
+      hipLaunchKernelGGL((PassKernel<P, T, false, ORD, MX>::k), grid, dim3(64), 0, s, v, ctl, sc);
   }
   return hipGetLastError();
 }
 
 // Wavefronts of the pass kernel (one per workgroup) that one CU holds at once.
-template <int P, int T, int ORD = 0>
+template <int P, int T, int ORD = 0, int MX = -1>
 int blocked_blocks_per_cu(bool pois) {
   int nb = 0;
   const hipError_t e =
       pois ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, true, ORD>::k), 64, 0)
+                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, true, ORD, MX>::k), 64, 0)
            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, false, ORD>::k), 64, 0);
+                 &nb, reinterpret_cast<const void *>(PassKernel<P, T, false, ORD, MX>::k), 64, 0);
   return e == hipSuccess ? nb : 0;
 }
 
