@@ -116,9 +116,9 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * iters_per_pass in 1..8 (iterations applied per HBM pass) and seg_rows, the
  * rows of output per wavefront (even, 8..1024).  0 in a field means "keep".
  * A new context reports both as 0 (chosen per solve).  Until iters_per_pass
- * is set, each plain solve uses 7 where the 7-deep pass kernel keeps two
- * wavefronts resident per SIMD for the solve's precision and problem (FP64
- * and FP32 Laplace problems on gfx950), else 6; batched FP64 solves always
+ * is set, each plain FP64 or FP32 solve uses 7, and a binary16 one 7 where
+ * the 7-deep pass kernel keeps two wavefronts resident per SIMD, else 6
+ * (6 on gfx950); batched FP64 solves always
  * run passes of 6 iterations (shorter ones only to finish a solve), and the
  * inner sweeps of batched and served mixed solves use the context's depth
  * capped at 6.  Until seg_rows is set, each plain solve picks it from the

@@ -113,9 +113,13 @@ int auto_seg_rows(sor_ctx *c, int prec, int n, int T, bool pois, int ord) {
 }
 
 int auto_depth(sor_ctx *c, int prec, bool pois) {
+  // FP64 and FP32: 7, which measured ahead of 6 (and 8) for Laplace and
+  // Poisson problems alike.  Binary16 storage: 7 where its 7-deep pass keeps
+  // two wavefronts on each of the CU's 4 SIMDs, else 6.
+  if (prec != kF16) return 7;
   int &occ = c->occ[prec][7][pois ? 1 : 0];
   if (occ <= 0) occ = std::max(1, blocked_blocks_per_cu(prec, 7, pois));
-  return occ >= 2 * 4 ? 7 : 6;      // two wavefronts on each of the CU's 4 SIMDs
+  return occ >= 2 * 4 ? 7 : 6;
 }
 
 sor_tiling tuned_tiling(sor_ctx *c, int prec, int n, bool pois) {

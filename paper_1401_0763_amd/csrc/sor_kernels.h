@@ -64,6 +64,23 @@ __device__ __forceinline__ double lane_permute(int addr, double x) {
                           lane_permute(addr, __double2loint(x)));
 }
 
+// The value of x in the adjacent lane (DPP wave shift by one lane: CTRL
+// kDppWaveShr1 reads lane i-1, kDppWaveShl1 lane i+1; the lane at the end
+// of the wave reads 0).  A 64-bit value moves as two 32-bit halves.  The
+// compiler keeps the wait state a DPP read needs after a vector write.
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_max(double x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
@@ -279,9 +296,13 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // All stages of one step update cells of the same parity v0 within a lane,
 // and the one neighbour that lies in the adjacent lane (left of cell 0 when
 // v0 = 0, right of cell V-1 when v0 = 1) is a cell that stage k-1 updated one
-// step earlier.  So every update sends that edge value across lanes at once
-// (xn[k+1]), and the exchange has a whole step to complete before stage k+1
-// uses it; stage 0's value comes from the next, not yet updated, row.
+// step earlier and that no stage has written since (stage 0: a cell of the
+// newly loaded row).  Red-black stages read it straight from the adjacent
+// lane's window register with a DPP wave shift, a vector move that needs
+// no LDS and no wait.  The block-parallel stages, which also need old
+// values, send each edge value across lanes through the LDS crossbar as it
+// is made (xn[k+1]), and that exchange has a whole step to complete before
+// stage k+1 uses it.
 //
 // Values near the strip and segment edges depend on cells outside the tile
 // and are wrong after enough stages (the dependency cone grows one cell per
@@ -479,7 +500,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   ct xs[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
-  if constexpr (ORD == 0 || BP) xs[0] = lane_permute(from_hi, w[1][0]);
+  if constexpr (BP) xs[0] = lane_permute(from_hi, w[1][0]);
   // Block-parallel: the red values that red stage t overwrote this step
   // (ob0), one step earlier (ob1) and two steps earlier (ob2), and the old
   // edge value received from the adjacent lane (xo, sent one step earlier).
@@ -528,9 +549,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       const int to = v0 == 1 ? from_lo : from_hi;
       ct xn[S];
       if constexpr (ORD == 0 || BP) {
-      // Stage 0 of the next step updates row r+1, still at level 0 here; its
-      // exchange goes first, since it is the first one used.
-      xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
+      // Block-parallel: stage 0 of the next step updates row r+1, still at
+      // level 0 here; its exchange goes first, since it is the first one
+      // used.
+      if constexpr (BP) xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
       if constexpr (BP) {
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -548,8 +570,19 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
           constexpr int v = v0 + 2 * decltype(JV)::value;
           const ct self = w[sq][v];
-          ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
-          ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
+          // Red-black: the neighbour in the adjacent lane is that lane's
+          // edge cell of the same row, which stage k-1 updated one step
+          // earlier and no stage has written since; a DPP wave shift reads
+          // it from there at the point of use.
+          ct left, right;
+          if constexpr (ORD == 0) {
+            left = v == 0 ? lane_shift<kDppWaveShr1>(w[sq][V - 1]) : w[sq][v == 0 ? 0 : v - 1];
+            right = v == V - 1 ? lane_shift<kDppWaveShl1>(w[sq][0])
+                               : w[sq][v == V - 1 ? 0 : v + 1];
+          } else {
+            left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
+            right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
+          }
           ct up = w[su][v], down = w[sd][v];
           if constexpr (BP && (k & 1)) {
             // Black half-sweep of iteration k/2: a red neighbour in another
@@ -598,18 +631,18 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
             const ct d = vabs(nu - self);
             m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
           }
-          if constexpr (v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
+          if constexpr (BP && v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
         } else if constexpr (k + 1 < S) {
           xn[k + 1] = (ct)0;                          // skipped: never read
         }
-        // Keep the exchange where it is issued (a scheduler would otherwise
-        // sink it next to its use a step later and wait for it there).  The
-        // full barrier is also kept for correctness: a schedule that let
-        // arithmetic cross it gave results that differed from the oracle's
-        // after hundreds of iterations on a large grid, a cause never isolated
-        // (a cross-lane read too close to the FP64 write of its source is the
-        // leading suspect), so no instruction may move across a stage.
+        // Keep an LDS exchange where it is issued (a scheduler would
+        // otherwise sink it next to its use a step later and wait for it
+        // there).  A schedule that let arithmetic cross this barrier once
+        // gave results that differed from the oracle's after hundreds of
+        // iterations on a large grid; the store-data wait state (buf_store)
+        // was missing then, and that schedule was not tried again, so no
+        // instruction moves across a stage.
         __builtin_amdgcn_sched_barrier(0);
       });
       } else if constexpr (ORD == 1) {

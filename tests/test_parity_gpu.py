@@ -401,16 +401,15 @@ def test_3d_and_orderings_subnormal_range_bitwise(sor, ctx):
 
 def test_automatic_depth(sor):
     """A fresh context chooses the depth per solve (reported as 0): 7 for FP64
-    Laplace problems, whose 7-deep pass keeps two wavefronts per SIMD, and 6
-    for FP64 Poisson problems, whose 7-deep pass does not.  Setting a depth
-    ends the automatic choice."""
+    and FP32, Laplace and Poisson problems alike.  Setting a depth ends the
+    automatic choice."""
     c = sor.Context(0)
     try:
         assert c.get_tiling(64) == (0, 0)
         assert c.tiling_for(64, 4096)[0] == 7
-        assert c.tiling_for(64, 4096, has_rhs=True)[0] == 6
-        assert c.tiling_for(32, 4096)[0] == 7          # 211 VGPRs: two per SIMD
-        assert c.tiling_for(32, 4096, has_rhs=True)[0] == 6
+        assert c.tiling_for(64, 4096, has_rhs=True)[0] == 7
+        assert c.tiling_for(32, 4096)[0] == 7
+        assert c.tiling_for(32, 4096, has_rhs=True)[0] == 7
         c.set_tiling(64, 0, 64)
         assert c.get_tiling(64) == (0, 64) and c.tiling_for(64, 4096) == (7, 64)
         c.set_tiling(64, 6, 0)
