@@ -119,7 +119,7 @@ sor_status sor_ctx_set_kernel(sor_ctx *ctx, int32_t kernel);
  * is set, each plain FP64 or FP32 solve uses 7, and a binary16 one 7 where
  * the 7-deep pass kernel keeps two wavefronts resident per SIMD, else 6
  * (6 on gfx950); batched FP64 solves always
- * run passes of 6 iterations (shorter ones only to finish a solve), and the
+ * run passes of 7 iterations (shorter ones only to finish a solve), and the
  * inner sweeps of batched and served mixed solves use the context's depth
  * capped at 6.  Until seg_rows is set, each plain solve picks it from the
  * grid side, so that a pass has about as many tiles as the device holds
@@ -478,7 +478,7 @@ sor_status sor_autotune(sor_ctx *ctx, int32_t bits, int32_t n, sor_tiling *best)
  * the chip and throughput, not one grid's pass latency, decides: solves a
  * scratch batch of identical n x n grids (enough for about 4096 tiles, at
  * most 256 grids and 1 GiB; 96 iterations each) once per candidate with
- * sor_batch_solve_f64 (bits 64: the fixed depth of 6 x 16..384 rows) or the
+ * sor_batch_solve_f64 (bits 64: the fixed depth of 7 x 16..384 rows) or the
  * inner sweeps of sor_batch_solve_mixed (bits 32 or 16: passes of 6
  * iterations x 16..384 rows), keeps the
  * fastest in the context's batched tuning table for n's size class (used by

@@ -229,6 +229,8 @@ hipError_t launch_mix_unpack(const BMGrid *grids, const int *slots, int count,
                              int max_n, hipStream_t s);
 hipError_t launch_mix_batch(int prec_lo, bool dyn, BMGrid *grids, BQueue *q, BItem *ring,
                             int waves, hipStream_t s);
+// Persistent wavefronts per CU of the mixed batched kernel: its occupancy,
+// capped at one per SIMD.
 int mix_waves_per_cu(int prec_lo, bool dyn);
 
 hipError_t launch_batch_pack(BGrid *grids, int count, int max_n,
@@ -237,12 +239,13 @@ hipError_t launch_batch_unpack(const BGrid *grids, int count, int max_n,
                                hipStream_t s);
 // Depth of the persistent batched FP64 sweep (its tile body has a source
 // term; grids without one read it as zero).  Measured on 512 grids of sides
-// 64-1024: depth 6 (one wavefront per SIMD) solves the batch in 0.29 s, 0.27
-// s with tuned tiles, against 0.35 s for depth 5 (the deepest with two
-// wavefronts per SIMD) and 0.29 / 0.33 s for depths 7 / 8.  A grid's passes
-// all have the tile geometry of this depth; shorter passes (re-runs, the last
-// iterations before a limit) run in a tail kernel.
-constexpr int kBatchT = 6;
+// 64-1024, one wavefront per SIMD: depth 7 solves the batch in 0.227 s
+// against 0.234 s for depth 6 (with the neighbour exchange through DPP;
+// before it, 0.29 s at depth 6 and 7, 0.35 s at depth 5 with two
+// wavefronts per SIMD, 0.33 s at depth 8).  A grid's passes all have the
+// tile geometry of this depth; shorter passes (re-runs, the last iterations
+// before a limit) run in a tail kernel.
+constexpr int kBatchT = 7;
 // Depth of the inner passes of the mixed-precision persistent kernel
 // (batched solves and the request server), measured the same way: the
 // 512-grid batch refined with FP32 inner sweeps to each grid's FP64 residual
@@ -255,6 +258,7 @@ constexpr int kMixTMax = 6;
 // tring = ring).  waves: persistent wavefronts.
 hipError_t launch_batch_f64(BGrid *grids, BQueue *q, BItem *ring, BQueue *tq, BItem *tring,
                             int waves, bool tail, hipStream_t s);
+// Its persistent wavefronts per CU: the occupancy, capped at one per SIMD.
 int batch_waves_per_cu_f64(bool tail);
 
 // Geometry of the blocked kernel for a precision, iterations-per-pass T and

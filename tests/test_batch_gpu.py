@@ -162,9 +162,9 @@ def test_batch_autotune_returns_supported_tiling_and_keeps_results(sor, ctx):
     and a plain solve keeps its own tiling."""
     plain_before = ctx.tiling_for(64, 100)
     T, seg = ctx.autotune_batch(64, 100)
-    # Batched FP64 passes have a fixed depth (6): only the tile height is
+    # Batched FP64 passes have a fixed depth (7): only the tile height is
     # tuned.
-    assert T == 6 and 16 <= seg <= 384
+    assert T == 7 and 16 <= seg <= 384
     assert ctx.tiling_for(64, 100) == plain_before
     grids = []
     for k in range(4):
