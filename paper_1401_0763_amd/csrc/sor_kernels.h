@@ -510,21 +510,16 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   for (int t = 0; t < TB; ++t) {
     ob0[t] = ob1[t] = ob2[t] = xo[t] = xon[t] = (ct)0;
   }
-  // Jacobi: every stage needs both cross-lane neighbours (xs from the lane
-  // below, xr from the lane above) and the row above its row at its own
-  // input level (pv), which the stage itself overwrote one step earlier.
+  // Jacobi: every stage needs the row above its row at its own input level
+  // (pv), which the stage itself overwrote one step earlier.
   constexpr int SJ = ORD == 2 ? S : 1;
-  ct xr[SJ];
   ct pv[SJ][V];
 #pragma unroll
   for (int k = 0; k < SJ; ++k) {
-    xr[k] = (ct)0;
 #pragma unroll
     for (int v = 0; v < V; ++v) pv[k][v] = (ct)0;
   }
   if constexpr (ORD == 2) {
-    xs[0] = lane_permute(from_lo, w[1][V - 1]);
-    xr[0] = lane_permute(from_hi, w[1][0]);
 #pragma unroll
     for (int v = 0; v < V; ++v) pv[0][v] = w[0][v];
   }
@@ -697,10 +692,9 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       // Jacobi: stage k is iteration k and updates every cell of row r-k
       // from level k of the rows above (pv[k]), at (its own, before any
       // write) and below (just updated by stage k-1), and of the cells in
-      // the neighbouring lanes (sent one step earlier).
-      ct xrn[S];
-      xn[0] = lane_permute(from_lo, w[(i + 2) % W][V - 1]);
-      xrn[0] = lane_permute(from_hi, w[(i + 2) % W][0]);
+      // the neighbouring lanes, which stage k-1 wrote one step earlier and
+      // which are read from those lanes' registers (DPP wave shifts) before
+      // this stage writes its own.
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
         constexpr int sq = ((i + 1 - k) % W + W) % W;
@@ -709,8 +703,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         static_for<0, V>([&](auto VV) __attribute__((always_inline)) {
           constexpr int v = decltype(VV)::value;
           const ct self = w[sq][v];
-          const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
-          const ct right = v == V - 1 ? xr[k] : w[sq][v == V - 1 ? 0 : v + 1];
+          const ct left = v == 0 ? lane_shift<kDppWaveShr1>(w[sq][V - 1])
+                                 : w[sq][v == 0 ? 0 : v - 1];
+          const ct right = v == V - 1 ? lane_shift<kDppWaveShl1>(w[sq][0])
+                                      : w[sq][v == V - 1 ? 0 : v + 1];
           ct s = (pv[k][v] + w[sd][v]) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
           const ct dg = vfma((ct)0.25, s, -self);
@@ -722,14 +718,8 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           pv[k][v] = w[sq][v];
           w[sq][v] = nw[v];
         }
-        if constexpr (k + 1 < S) {
-          xn[k + 1] = lane_permute(from_lo, nw[V - 1]);
-          xrn[k + 1] = lane_permute(from_hi, nw[0]);
-        }
         __builtin_amdgcn_sched_barrier(0);
       });
-#pragma unroll
-      for (int k = 0; k < S; ++k) xr[k] = xrn[k];
       }
 #pragma unroll
       for (int k = 0; k < S; ++k) xs[k] = xn[k];
