@@ -493,10 +493,12 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     load_row(a + decltype(SP)::value, SP);
   });
 
-  // Cross-lane neighbour of stage k at the coming step (see above).  At the
-  // first step (v0 = 1) stage 0 needs the right neighbour of cell V-1 of row
-  // a+1 (slot 1), i.e. cell 0 of the lane above; deeper stages start on rows
-  // above the tile, whose values never reach core cells.
+  // Block-parallel: cross-lane neighbour of stage k at the coming step,
+  // received through the LDS crossbar (see above; the other orderings read
+  // it with DPP at the point of use).  At the first step (v0 = 1) stage 0
+  // needs the right neighbour of cell V-1 of row a+1 (slot 1), i.e. cell 0
+  // of the lane above; deeper stages start on rows above the tile, whose
+  // values never reach core cells.
   ct xs[S];
 #pragma unroll
   for (int k = 0; k < S; ++k) xs[k] = (ct)0;
@@ -628,7 +630,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           }
           if constexpr (BP && v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
-        } else if constexpr (k + 1 < S) {
+        } else if constexpr (BP && k + 1 < S) {
           xn[k + 1] = (ct)0;                          // skipped: never read
         }
         // Keep an LDS exchange where it is issued (a scheduler would
@@ -647,18 +649,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       // the static parity of 1+i-k; the cells a stage updates in this lane
       // have the static parity vpar(k, q) (none for colour 0 on odd rows and
       // colour 3 on even rows).  Stage k+1 takes the same row at the next
-      // step, so after stage k this lane sends the edge cell that stage k+1
-      // will need from it.
+      // step, so the edge cell it needs from the adjacent lane is that lane's
+      // cell as stage k left it; it is read from that lane's register (DPP
+      // wave shift) at the point of use.
       auto vpar = [](int k, int pq) constexpr {
         const int c = k % 3;
         return c == 0 ? (pq == 0 ? 0 : -1) : c == 1 ? ((pq + 1) & 1) : (pq == 1 ? 1 : -1);
       };
-      {
-        constexpr int pn = i & 1;                 // parity of row r+1
-        constexpr int vn = vpar(0, pn);
-        if constexpr (vn == 0) xn[0] = lane_permute(from_lo, w[(i + 2) % W][V - 1]);
-        else if constexpr (vn == 1) xn[0] = lane_permute(from_hi, w[(i + 2) % W][0]);
-      }
       static_for<0, S>([&](auto K) __attribute__((always_inline)) {
         constexpr int k = decltype(K)::value;
         constexpr int sq = ((i + 1 - k) % W + W) % W;
@@ -670,8 +667,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
             constexpr int v = vp + 2 * decltype(JV)::value;
             const ct self = w[sq][v];
-            const ct left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
-            const ct right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
+            const ct left = v == 0 ? lane_shift<kDppWaveShr1>(w[sq][V - 1])
+                                   : w[sq][v == 0 ? 0 : v - 1];
+            const ct right = v == V - 1 ? lane_shift<kDppWaveShl1>(w[sq][0])
+                                        : w[sq][v == V - 1 ? 0 : v + 1];
             ct s = (w[su][v] + w[sd][v]) + (left + right);
             if constexpr (POIS) s = s + fw[sq][v];
             const ct dg = vfma((ct)0.25, s, -self);
@@ -680,11 +679,6 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
             w[sq][v] = nu;
             m[k / 3] = vmax(m[k / 3], d * wc[sq]);
           });
-        }
-        if constexpr (k + 1 < S) {
-          constexpr int vq = vpar(k + 1, pq);
-          if constexpr (vq == 0) xn[k + 1] = lane_permute(from_lo, w[sq][V - 1]);
-          else if constexpr (vq == 1) xn[k + 1] = lane_permute(from_hi, w[sq][0]);
         }
         __builtin_amdgcn_sched_barrier(0);
       });
@@ -721,8 +715,10 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         __builtin_amdgcn_sched_barrier(0);
       });
       }
+      if constexpr (BP) {
 #pragma unroll
-      for (int k = 0; k < S; ++k) xs[k] = xn[k];
+        for (int k = 0; k < S; ++k) xs[k] = xn[k];
+      }
       if constexpr (BP && !BPE) {
 #pragma unroll
         for (int t = 0; t < T; ++t) xo[t] = xon[t];
