@@ -44,25 +44,6 @@ __device__ __forceinline__ void static_for(F &&f) {
   }
 }
 
-// ---------------------------------------------------------------------------
-// Cross-lane moves through the LDS crossbar (ds_bpermute): lane i receives
-// the value of lane src.  The permute's completion is tracked by the LDS
-// counter like any LDS read, so it needs no hand-placed wait states.  (In
-// this sweep the DPP wave shifts, which use no LDS bandwidth, produced
-// lane-dependent results that varied between runs when their source had just
-// been written by an FP64 operation, so they are not used.)  The wave-edge
-// lanes receive the value from the opposite edge; they only feed halo cells.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int lane_permute(int addr, int x) {
-  return __builtin_amdgcn_ds_bpermute(addr, x);
-}
-__device__ __forceinline__ float lane_permute(int addr, float x) {
-  return __int_as_float(lane_permute(addr, __float_as_int(x)));
-}
-__device__ __forceinline__ double lane_permute(int addr, double x) {
-  return __hiloint2double(lane_permute(addr, __double2hiint(x)),
-                          lane_permute(addr, __double2loint(x)));
-}
 
 // The value of x in the adjacent lane (DPP wave shift by one lane: CTRL
 // kDppWaveShr1 reads lane i-1, kDppWaveShl1 lane i+1; the lane at the end
@@ -297,12 +278,12 @@ __host__ __device__ constexpr int order_window_rows(int ord, int T) {
 // and the one neighbour that lies in the adjacent lane (left of cell 0 when
 // v0 = 0, right of cell V-1 when v0 = 1) is a cell that stage k-1 updated one
 // step earlier and that no stage has written since (stage 0: a cell of the
-// newly loaded row).  Red-black stages read it straight from the adjacent
-// lane's window register with a DPP wave shift, a vector move that needs
-// no LDS and no wait.  The block-parallel stages, which also need old
-// values, send each edge value across lanes through the LDS crossbar as it
-// is made (xn[k+1]), and that exchange has a whole step to complete before
-// stage k+1 uses it.
+// newly loaded row).  Each stage reads it straight from the adjacent lane's
+// window register with a DPP wave shift (lane_shift), a vector move that
+// needs no LDS; the block-parallel stages read an old value the same way
+// from the adjacent lane's ob1.  (An earlier form sent every edge value
+// through the LDS crossbar as it was made, 2 permutes per stage, which
+// bounded the pass.)
 //
 // Values near the strip and segment edges depend on cells outside the tile
 // and are wrong after enough stages (the dependency cone grows one cell per
@@ -413,8 +394,6 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     rf = g.F ? make_rsrc((const st *)g.F + tile_off, extent) : make_rsrc(g.in, 0u);
   const unsigned lane_off = (unsigned)(lane * V * ESZ);
   const unsigned st_off = lane_store ? lane_off : kDrop;
-  const int from_lo = ((lane + 63) & 63) << 2;   // permute address: lane - 1
-  const int from_hi = ((lane + 1) & 63) << 2;    // permute address: lane + 1
   // Non-finite test of the stored interior cells: the largest high word (sign
   // cleared) of their bit patterns is at least that of infinity exactly when
   // one of them is an infinity or a NaN; integer operations, two per cell.
@@ -493,24 +472,14 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     load_row(a + decltype(SP)::value, SP);
   });
 
-  // Block-parallel: cross-lane neighbour of stage k at the coming step,
-  // received through the LDS crossbar (see above; the other orderings read
-  // it with DPP at the point of use).  At the first step (v0 = 1) stage 0
-  // needs the right neighbour of cell V-1 of row a+1 (slot 1), i.e. cell 0
-  // of the lane above; deeper stages start on rows above the tile, whose
-  // values never reach core cells.
-  ct xs[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) xs[k] = (ct)0;
-  if constexpr (BP) xs[0] = lane_permute(from_hi, w[1][0]);
   // Block-parallel: the red values that red stage t overwrote this step
-  // (ob0), one step earlier (ob1) and two steps earlier (ob2), and the old
-  // edge value received from the adjacent lane (xo, sent one step earlier).
+  // (ob0), one step earlier (ob1) and two steps earlier (ob2); an old value
+  // in the adjacent lane is that lane's ob1.
   constexpr int TB = BP ? T : 1;
-  ct ob0[TB], ob1[TB], ob2[TB], xo[TB], xon[TB];
+  ct ob0[TB], ob1[TB], ob2[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
-    ob0[t] = ob1[t] = ob2[t] = xo[t] = xon[t] = (ct)0;
+    ob0[t] = ob1[t] = ob2[t] = (ct)0;
   }
   // Jacobi: every stage needs the row above its row at its own input level
   // (pv), which the stage itself overwrote one step earlier.
@@ -541,15 +510,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
       // Cells of colour k&1 in this lane at stage k: (q + col0 + v + k) even,
       // and q + k = r has the parity of 1 + i because a, base and W are even.
       constexpr int v0 = (1 + i) & 1;
-      // Edge cell whose value the next step's stages need from this lane.
-      constexpr int ve = v0 == 1 ? V - 1 : 0;
-      const int to = v0 == 1 ? from_lo : from_hi;
-      ct xn[S];
       if constexpr (ORD == 0 || BP) {
-      // Block-parallel: stage 0 of the next step updates row r+1, still at
-      // level 0 here; its exchange goes first, since it is the first one
-      // used.
-      if constexpr (BP) xn[0] = lane_permute(to, w[(i + 2) % W][ve]);
       if constexpr (BP) {
 #pragma unroll
         for (int t = 0; t < T; ++t) {
@@ -567,19 +528,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         static_for<0, V / 2>([&](auto JV) __attribute__((always_inline)) {
           constexpr int v = v0 + 2 * decltype(JV)::value;
           const ct self = w[sq][v];
-          // Red-black: the neighbour in the adjacent lane is that lane's
-          // edge cell of the same row, which stage k-1 updated one step
-          // earlier and no stage has written since; a DPP wave shift reads
-          // it from there at the point of use.
-          ct left, right;
-          if constexpr (ORD == 0) {
-            left = v == 0 ? lane_shift<kDppWaveShr1>(w[sq][V - 1]) : w[sq][v == 0 ? 0 : v - 1];
-            right = v == V - 1 ? lane_shift<kDppWaveShl1>(w[sq][0])
-                               : w[sq][v == V - 1 ? 0 : v + 1];
-          } else {
-            left = v == 0 ? xs[k] : w[sq][v == 0 ? 0 : v - 1];
-            right = v == V - 1 ? xs[k] : w[sq][v == V - 1 ? 0 : v + 1];
-          }
+          // The neighbour in the adjacent lane is that lane's edge cell of
+          // the same row, which stage k-1 updated one step earlier and no
+          // stage has written since; a DPP wave shift reads it from there
+          // at the point of use.
+          ct left = v == 0 ? lane_shift<kDppWaveShr1>(w[sq][V - 1]) : w[sq][v == 0 ? 0 : v - 1];
+          ct right = v == V - 1 ? lane_shift<kDppWaveShl1>(w[sq][0])
+                                : w[sq][v == V - 1 ? 0 : v + 1];
           ct up = w[su][v], down = w[sd][v];
           if constexpr (BP && (k & 1)) {
             // Black half-sweep of iteration k/2: a red neighbour in another
@@ -604,13 +559,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
               if constexpr (v == 0) right = pick(ob1[t], right, hx_in);
               else left = pick(ob1[t], left, hx_in);
             } else {
-              left = pick(v == 0 ? xo[t] : ob1[t], left, hx_w[v]);
-              right = pick(v == V - 1 ? xo[t] : ob1[t], right, hx_e[v]);
+              left = pick(v == 0 ? lane_shift<kDppWaveShr1>(ob1[t]) : ob1[t], left, hx_w[v]);
+              right = pick(v == V - 1 ? lane_shift<kDppWaveShl1>(ob1[t]) : ob1[t], right,
+                           hx_e[v]);
             }
           }
           if constexpr (BP && !(k & 1)) {
             ob0[k >> 1] = self;
-            if constexpr (v == ve && !BPE) xon[k >> 1] = lane_permute(to, self);
           }
           ct s = (up + down) + (left + right);
           if constexpr (POIS) s = s + fw[sq][v];
@@ -628,18 +583,13 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
             const ct d = vabs(nu - self);
             m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
           }
-          if constexpr (BP && v == ve && k + 1 < S) xn[k + 1] = lane_permute(to, nu);
         });
-        } else if constexpr (BP && k + 1 < S) {
-          xn[k + 1] = (ct)0;                          // skipped: never read
         }
-        // Keep an LDS exchange where it is issued (a scheduler would
-        // otherwise sink it next to its use a step later and wait for it
-        // there).  A schedule that let arithmetic cross this barrier once
-        // gave results that differed from the oracle's after hundreds of
-        // iterations on a large grid; the store-data wait state (buf_store)
-        // was missing then, and that schedule was not tried again, so no
-        // instruction moves across a stage.
+        // No instruction moves across a stage.  A schedule that let
+        // arithmetic cross this barrier once gave results that differed
+        // from the oracle's after hundreds of iterations on a large grid;
+        // the store-data wait state (buf_store) was missing then, and that
+        // schedule was not tried again.
         __builtin_amdgcn_sched_barrier(0);
       });
       } else if constexpr (ORD == 1) {
@@ -714,14 +664,6 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
         }
         __builtin_amdgcn_sched_barrier(0);
       });
-      }
-      if constexpr (BP) {
-#pragma unroll
-        for (int k = 0; k < S; ++k) xs[k] = xn[k];
-      }
-      if constexpr (BP && !BPE) {
-#pragma unroll
-        for (int t = 0; t < T; ++t) xo[t] = xon[t];
       }
       // Row r-S+1 has had all S half-sweeps: store it if it is a core row.
       constexpr int so = ((i + 2 - S) % W + W) % W;
