@@ -495,7 +495,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
     for (int v = 0; v < V; ++v) pv[0][v] = w[0][v];
   }
 
-  // Wait here for the prologue's loads and permute.  The loop head joins
+  // Wait here for the prologue's loads.  The loop head joins
   // this path with the loop's back edge; without the wait the compiler takes
   // the prologue's most recent load as pending there and drains the memory
   // queue at the head of every chunk instead of once per tile.
