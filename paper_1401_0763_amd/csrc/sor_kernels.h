@@ -449,7 +449,7 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
   // Row rn (clamped to the tile) into window slot SP, with its attributes.
   auto load_row = [&](int rn, auto SP) __attribute__((always_inline)) {
     constexpr int sp = decltype(SP)::value;
-    wc[sp] = (rn >= rlo && rn < rhi) ? (ct)1 : (ct)0;
+    if constexpr (MX < 0 || P != kF64) wc[sp] = (rn >= rlo && rn < rhi) ? (ct)1 : (ct)0;
     wr[sp] = (rn >= 1 && rn <= n) ? (ct)1 : (ct)0;
     if constexpr (BP) {
       const unsigned bit = 1u << sp;
@@ -581,7 +581,19 @@ __device__ __forceinline__ void blocked_tile(const GridView &g, int tile,
           w[sq][v] = nu;
           if constexpr (MX < 0 || (k >> 1) == MX) {
             const ct d = vabs(nu - self);
-            m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
+            if constexpr (MX < 0 || P != kF64) {
+              m[k >> 1] = vmax(m[k >> 1], d * wc[sq]);
+            } else {
+              // One maximum per FP64 pass: the row's weight is formed where
+              // it is used (two stages per step) instead of kept per window
+              // slot, which saves the slots' SGPRs (0.8 % of the 7-deep
+              // pass).  Not for FP32: its 7-deep Poisson pass would then fit
+              // two wavefronts per SIMD, and the tiles sized for two ran the
+              // inner sweeps of the mixed solve at 1400 against 1580 GLUP/s.
+              const int q = r - k;
+              const ct wq = ((unsigned)(q - rlo) < (unsigned)(rhi - rlo)) ? (ct)1 : (ct)0;
+              m[k >> 1] = vmax(m[k >> 1], d * wq);
+            }
           }
         });
         }
